@@ -1,0 +1,182 @@
+"""Benchmark of the voxel-wise structure-tensor path on one MI355X.
+
+Workload: the 512^3 uint16 helical phantom with its binary annulus mask,
+sigma = 1.5, rho = 4 (truncate 4), outputs e3 + FA + HA + IA for every voxel.
+One step = one st_compute call over the whole volume, inputs resident in HBM.
+Prints one JSON line (see the "metric" key) with a roofline object for the
+dominant kernel (durations from HIP events recorded around every kernel on
+the launch stream inside the timed region) and the FP64 CPU oracle timed on a
+bounded crop of the same phantom.
+
+  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gvoxels/s (HBM GB/s vs peak) plain vs surrogate at ≤2° fibre-angle error"
+HBM_PEAK_GBS = 8000.0
+# FP32 (packed FP32 ops are not used) and FP64 FMA issue rate: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flops x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6432
+
+SHAPE = (512, 512, 512)
+SIGMA, RHO, TRUNCATE = 1.5, 4.0, 4.0
+OUTPUTS = ("e3", "fa", "ha", "ia")
+
+# Algorithmic HBM bytes per voxel and per launch of each kernel (input read once,
+# output written once; no halo re-reads), for this workload.
+ALG_BYTES_PER_VOXEL = {
+    "grad_z": 2 + 8,                  # u16 in, G_z V and D_z V out
+    "grad_y": (4 + 8 + 4 + 4) / 2,    # two launches: (1 in, 2 out) and (1 in, 1 out)
+    "grad_x_outer": 12 + 24,          # 3 planes in, 6 products out
+    "integrate_z": 24 + 24,
+    "integrate_y": 24 + 24,
+    "integrate_x_eigen": 24 + 1 + 12 + 12,  # S + mask in; e3, FA, HA, IA out
+}
+KERNEL_SOURCES = ["k_strided_impl.h", "k_xpass_impl.h", "st_device.h", "st_api.hip"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_07476_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, nvox, launches):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", "traffic_headline.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(vol_u16, mask_u8, center, direction):
+    """FP64 oracle on a bounded crop of the same phantom (single process)."""
+    import numpy as np
+    import psutil
+
+    import oracle
+    s = 160
+    z0, y0, x0 = 176, 96, 176
+    crop = vol_u16[z0:z0 + s, y0:y0 + s, x0:x0 + s].cpu().numpy()
+    mcrop = mask_u8[z0:z0 + s, y0:y0 + s, x0:x0 + s].cpu().numpy()
+    proc = psutil.Process()
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    oracle.compute(crop, mcrop, SIGMA, RHO, TRUNCATE, axis_center=center, axis_direction=direction,
+                   origin=(z0, y0, x0))
+    wall = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    nvox = crop.size
+    return {"value": nvox / wall / 1e9, "unit": "Gvoxels/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": f"{s}^3 crop at (z,y,x)=({z0},{y0},{x0}) of the same phantom+mask, whole path "
+                      f"(tensor, eigen, FA, HA, IA) in FP64 NumPy, {nvox} voxels in {wall:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the structure-tensor path here is built and timed on "
+              "a single MI355X (multi-GPU z-slab sharding is a design note, not implemented).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_07476_amd as st
+    from phantom import helix
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    st.load_library()
+    spec = helix.spec_headline_u16(shape=SHAPE)
+    ph = helix.generate(spec, device=dev)
+    vol, mask = ph["volume"], ph["mask"]
+    nvox = vol.numel()
+    nz, ny, nx = SHAPE
+    out = {k: torch.empty(((3,) if k == "e3" else ()) + SHAPE, dtype=torch.float32, device=dev)
+           for k in OUTPUTS}
+    ws = torch.empty(st.st_workspace_bytes(SHAPE), dtype=torch.uint8, device=dev)
+
+    def step():
+        st.st_compute(vol, SIGMA, RHO, TRUNCATE, mask=mask, axis_center=ph["center"],
+                      axis_direction=ph["direction"], outputs=OUTPUTS, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    st.profile_reset()
+    st.profile_enable(True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        step()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    st.profile_enable(False)
+    kern = st.profile_read()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    value = nvox * args.steps / (total_ms / 1e3) / 1e9
+
+    # dominant kernel
+    dom = max(kern.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dlaunch) = dom
+    avg_s = dms / dlaunch / 1e3
+    bytes_per_launch = ALG_BYTES_PER_VOXEL[dname] * nvox
+    achieved = bytes_per_launch / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dname, nvox, dlaunch),
+            "kernel": dname, "avg_launch_ms": round(avg_s * 1e3, 4),
+            "alg_bytes_per_voxel": ALG_BYTES_PER_VOXEL[dname]}
+    per_kernel = {k: {"avg_ms": round(v[0] / v[1], 4), "launches_per_step": v[1] / args.steps,
+                      "alg_GBps": round(ALG_BYTES_PER_VOXEL[k] * nvox / (v[0] / v[1] / 1e3) / 1e9, 1)}
+                  for k, v in kern.items()}
+
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 uint16 helical rod-lattice phantom + annulus mask, sigma=1.5, "
+                               "rho=4, truncate=4; outputs e3, FA, HA, IA (plain path)",
+                   "shape": list(SHAPE), "sigma": SIGMA, "rho": RHO, "input": "uint16",
+                   "accumulate": "f32", "eigensolve": "f64"},
+        "roofline": roof,
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(vol, mask, ph["center"], ph["direction"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

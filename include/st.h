@@ -1,0 +1,164 @@
+/*
+ * st.h -- C ABI of the MI355X (gfx950) voxel-wise 3D structure-tensor library.
+ *
+ * The library computes, for every voxel of a 3-D intensity volume, the local
+ * fibre orientation of the paper's orientation module (Architecture section;
+ * Figure 1(a)-(c)): Gaussian-derivative gradients at scale sigma, the
+ * six-component gradient outer product, Gaussian integration at scale rho,
+ * a 3x3 symmetric eigen-decomposition whose smallest-eigenvalue vector e3 is
+ * the fibre direction, fractional anisotropy (FA), and helix / intrusion
+ * angles (HA, IA) in a cylindrical frame about a given left-ventricular axis.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are C-order [nz][ny][nx] (x fastest), unit isotropic spacing.
+ *    Vectors (e3, axis centre, axis direction) are in (z, y, x) order.
+ *  - Every array pointer is a DEVICE pointer allocated by the caller, except
+ *    axis_center / axis_direction, which are HOST pointers to 3 doubles.
+ *    The caller owns all memory; the library never frees caller memory.
+ *  - Work is only enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *    the default stream). Results are valid once the caller synchronises the
+ *    stream; the library never synchronises the device.
+ *  - Arguments are validated on the host before any HIP call; on error the
+ *    function returns a non-zero status, enqueues nothing and leaves every
+ *    output untouched. st_last_error() then returns a thread-local message.
+ *  - Results are bitwise deterministic for a given device and arguments
+ *    (no atomics, fixed summation order).
+ *
+ * Filters (reading of the paper, which names the structure tensor but prints
+ * no formula): for scale s and `truncate` t the kernel radius is
+ * R = floor(t*s + 0.5); taps w0(k) = exp(-k^2/(2 s^2)) / sum_j exp(-j^2/(2 s^2))
+ * and w1(k) = (k/s^2) w0(k) for k in [-R, R], applied as 1-D correlations with
+ * half-sample symmetric reflection at every face.  Accumulation is float32;
+ * the eigen-decomposition, FA and the frame run in float64.
+ */
+#ifndef ST_H_
+#define ST_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every entry point. */
+#define ST_OK 0
+#define ST_ERR_INVALID_ARG 1   /* a pointer, size, scale or axis is invalid */
+#define ST_ERR_UNSUPPORTED 2   /* valid request this build cannot serve (e.g. kernel radius > 32) */
+#define ST_ERR_OUT_OF_MEMORY 3 /* the library could not allocate its workspace */
+#define ST_ERR_DEVICE 4        /* a HIP call failed; st_last_error() holds hipGetErrorString */
+
+/* Input element types. */
+#define ST_DTYPE_U16 1
+#define ST_DTYPE_F32 2
+
+/* Bits of the per-voxel flags output. */
+#define ST_FLAG_DEGENERATE 1   /* trace <= 0 or (lambda2 - lambda3)/trace < 1e-3 */
+#define ST_FLAG_OUTSIDE_MASK 2 /* mask == 0: every other output of the voxel is 0 */
+#define ST_FLAG_ON_AXIS 4      /* distance to the axis < 1e-9: HA = IA = 0 */
+
+/* Largest kernel radius R = floor(truncate*scale + 0.5) served, for sigma and rho. */
+#define ST_MAX_RADIUS_SIGMA 16
+#define ST_MAX_RADIUS_RHO 32
+
+/* Library version, 10000*major + 100*minor + patch. */
+int st_version(void);
+
+/* Message describing the last non-OK status returned on this thread ("" if none). */
+const char* st_last_error(void);
+
+/* Kernel radius floor(truncate*scale + 0.5), or -1 if scale/truncate are not finite and > 0. */
+int st_filter_radius(double scale, double truncate);
+
+/*
+ * Bytes of device workspace st_compute needs for an nz*ny*nx volume
+ * (12 float32 planes of nz*ny*nx values, 256-byte aligned).  Returns 0 on
+ * invalid sizes (non-positive, or a byte count that overflows size_t).
+ */
+size_t st_workspace_bytes(int64_t nz, int64_t ny, int64_t nx);
+
+/*
+ * st_compute -- the whole orientation path in one call (paper: Figure 1(a)-(c),
+ * orientation module of the Architecture section).
+ *
+ *  volume          device, nz*ny*nx elements of `dtype` (ST_DTYPE_U16 or ST_DTYPE_F32)
+ *  mask            device, nz*ny*nx uint8 (nonzero = tissue) or NULL (every voxel is tissue).
+ *                  The tensor is computed from the raw intensities; the mask only
+ *                  gates the outputs (outside: e3 = evals = FA = HA = IA = 0, flags = 2).
+ *  nz, ny, nx      sizes, each >= 1
+ *  sigma, rho      gradient and integration scales in voxels (> 0, finite)
+ *  truncate        kernel half-width in units of the scale (> 0; 4.0 is customary);
+ *                  radii above ST_MAX_RADIUS_SIGMA / ST_MAX_RADIUS_RHO -> ST_ERR_UNSUPPORTED
+ *  axis_center     host double[3] (z, y, x) voxel coordinates of a point on the axis, or NULL
+ *  axis_direction  host double[3] (z, y, x) axis direction (any non-zero length);
+ *                  NULL iff axis_center is NULL.  Without an axis, ha and ia must be NULL.
+ *  e3              device float[3][nz*ny*nx] (SoA: z, y, x planes), unit fibre vectors
+ *                  with canonical sign (largest-|.| component positive, ties to z then y), or NULL
+ *  evals           device float[3][nz*ny*nx], lambda1 >= lambda2 >= lambda3, or NULL
+ *  fa, ha, ia      device float[nz*ny*nx] (HA, IA in radians, in [-pi/2, pi/2]), or NULL
+ *  flags           device uint8[nz*ny*nx] (ST_FLAG_* bits), or NULL
+ *  workspace       device scratch of at least st_workspace_bytes(nz, ny, nx) bytes, or NULL
+ *                  with workspace_bytes == 0: the library then allocates it stream-ordered
+ *                  (hipMallocAsync) and frees it after the last kernel (hipFreeAsync).
+ *  stream          hipStream_t on which all work is enqueued
+ *
+ * HA = atan2(f_a sgn f_t, |f_t|) and IA = atan2(f_r sgn f_t, |f_t|) with f_* the
+ * components of e3 on the frame e_r (radial), e_t = a x e_r (right-handed) and a
+ * (axis), sgn(0) = +1.  Buffers must not overlap each other or the workspace.
+ */
+int st_compute(const void* volume, int dtype, const uint8_t* mask,
+               int64_t nz, int64_t ny, int64_t nx,
+               double sigma, double rho, double truncate,
+               const double* axis_center, const double* axis_direction,
+               float* e3, float* evals, float* fa, float* ha, float* ia, uint8_t* flags,
+               void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * st_angles -- helix and intrusion angles of a given fibre field about a new
+ * axis (paper: Figure 1(c), cylindrical coordinate rotation), without
+ * recomputing the tensor.
+ *
+ *  e3              device float[3][nz*ny*nx] (SoA z, y, x); need not be normalised
+ *                  (a zero vector gives HA = IA = 0)
+ *  mask            device uint8[nz*ny*nx] or NULL; outside: HA = IA = 0
+ *  axis_center, axis_direction   host double[3] each, required
+ *  ha, ia          device float[nz*ny*nx] outputs (radians); either may be NULL
+ *  flags           device uint8[nz*ny*nx] or NULL: receives ST_FLAG_OUTSIDE_MASK and
+ *                  ST_FLAG_ON_AXIS only (never ST_FLAG_DEGENERATE)
+ */
+int st_angles(const float* e3, const uint8_t* mask,
+              int64_t nz, int64_t ny, int64_t nx,
+              const double* axis_center, const double* axis_direction,
+              float* ha, float* ia, uint8_t* flags, void* stream);
+
+/*
+ * st_surrogate_infer -- learned fibre-orientation surrogate with fallback to
+ * st_compute where its confidence is below `min_confidence`.  Not provided by
+ * this build: validates nothing and returns ST_ERR_UNSUPPORTED.
+ */
+int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
+                       int64_t nz, int64_t ny, int64_t nx,
+                       const void* weights, size_t weights_bytes, double min_confidence,
+                       double sigma, double rho, double truncate,
+                       const double* axis_center, const double* axis_direction,
+                       float* e3, float* fa, float* ha, float* ia, float* confidence,
+                       void* stream);
+
+/*
+ * Kernel timing for measurement tools.  While enabled, every kernel launched
+ * by st_compute / st_angles is bracketed by HIP events recorded on the same
+ * stream.  st_profile_read() waits for those events (host-side), adds their
+ * elapsed times into per-kernel totals and returns the number of distinct
+ * kernels seen; entry i's name, total milliseconds and launch count are
+ * written to the optional outputs.  Not thread-safe; off by default.
+ */
+int st_profile_enable(int on);
+int st_profile_reset(void);
+int st_profile_read(int index, char* name, size_t name_len, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ST_H_ */

@@ -1,0 +1,245 @@
+"""ctypes binding of libst.so: argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; this module checks
+tensor types, allocates outputs and the workspace with PyTorch (device memory
+and streams are all PyTorch is used for) and passes raw pointers.  If the
+library is missing it raises -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libst.so")
+
+ST_OK = 0
+ST_ERR_INVALID_ARG = 1
+ST_ERR_UNSUPPORTED = 2
+ST_ERR_OUT_OF_MEMORY = 3
+ST_ERR_DEVICE = 4
+ST_DTYPE_U16 = 1
+ST_DTYPE_F32 = 2
+ST_FLAG_DEGENERATE = 1
+ST_FLAG_OUTSIDE_MASK = 2
+ST_FLAG_ON_AXIS = 4
+
+# exported symbols and their C signatures (restype, argtypes)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "st_version": (ctypes.c_int, []),
+    "st_last_error": (ctypes.c_char_p, []),
+    "st_filter_radius": (ctypes.c_int, [_D, _D]),
+    "st_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
+    "st_compute": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _D, _D, _D, _DP, _DP,
+                                  _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_angles": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _DP, _DP, _P, _P, _P, _P]),
+    "st_surrogate_infer": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _SZ, _D,
+                                          _D, _D, _D, _DP, _DP, _P, _P, _P, _P, _P, _P]),
+    "st_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "st_profile_reset": (ctypes.c_int, []),
+    "st_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, _SZ, _DP,
+                                       ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+class StError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"st error {code}: {message}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libst.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_2508_07476_amd.csrc.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != ST_OK:
+        msg = load_library().st_last_error()
+        raise StError(code, msg.decode() if msg else "")
+
+
+def _vec3(v) -> Optional[ctypes.Array]:
+    if v is None:
+        return None
+    vals = [float(x) for x in v]
+    if len(vals) != 3:
+        raise ValueError("axis vectors have 3 (z, y, x) components")
+    return (ctypes.c_double * 3)(*vals)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def st_version() -> int:
+    return load_library().st_version()
+
+
+def st_filter_radius(scale: float, truncate: float = 4.0) -> int:
+    return load_library().st_filter_radius(scale, truncate)
+
+
+def st_workspace_bytes(shape: Sequence[int]) -> int:
+    nz, ny, nx = (int(s) for s in shape)
+    return load_library().st_workspace_bytes(nz, ny, nx)
+
+
+def _require_device_tensor(name, t, dtypes, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device, got {t.device}")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} dtype {t.dtype} not in {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be C-contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+ALL_OUTPUTS = ("e3", "evals", "fa", "ha", "ia", "flags")
+
+
+def st_compute(volume, sigma: float, rho: float, truncate: float = 4.0, mask=None,
+               axis_center=None, axis_direction=None,
+               outputs: Iterable[str] = ("e3", "fa", "ha", "ia", "flags"),
+               out: Optional[dict] = None, workspace=None):
+    """Run the whole structure-tensor path on ``volume`` (nz, ny, nx) uint16/float32 CUDA tensor.
+
+    Returns a dict with the requested outputs: ``e3`` / ``evals`` (3, nz, ny, nx)
+    float32, ``fa`` / ``ha`` / ``ia`` (nz, ny, nx) float32, ``flags`` uint8.
+    ``out`` may supply preallocated output tensors; ``workspace`` a uint8 tensor of
+    at least ``st_workspace_bytes(volume.shape)`` bytes.  Work is enqueued on the
+    current stream of the volume's device.
+    """
+    import torch
+    lib = load_library()
+    _require_device_tensor("volume", volume, (torch.uint16, torch.float32))
+    if volume.dim() != 3:
+        raise ValueError("volume must be 3-D (nz, ny, nx)")
+    nz, ny, nx = volume.shape
+    dev = volume.device
+    dtype = ST_DTYPE_U16 if volume.dtype == torch.uint16 else ST_DTYPE_F32
+    if mask is not None:
+        _require_device_tensor("mask", mask, (torch.uint8, torch.bool), (nz, ny, nx))
+        if mask.dtype == torch.bool:
+            mask = mask.view(torch.uint8)
+    outputs = tuple(outputs)
+    for k in outputs:
+        if k not in ALL_OUTPUTS:
+            raise ValueError(f"unknown output {k!r}")
+    res = {}
+    out = out or {}
+    for k in outputs:
+        shape = (3, nz, ny, nx) if k in ("e3", "evals") else (nz, ny, nx)
+        dt = torch.uint8 if k == "flags" else torch.float32
+        if k in out:
+            _require_device_tensor(k, out[k], (dt,), shape)
+            res[k] = out[k]
+        else:
+            res[k] = torch.empty(shape, dtype=dt, device=dev)
+    if workspace is None:
+        workspace = torch.empty(st_workspace_bytes((nz, ny, nx)), dtype=torch.uint8, device=dev)
+    else:
+        _require_device_tensor("workspace", workspace, (torch.uint8,))
+    ws_bytes = workspace.numel()
+    with torch.cuda.device(dev):
+        code = lib.st_compute(_ptr(volume), dtype, _ptr(mask), nz, ny, nx, float(sigma), float(rho),
+                              float(truncate), _vec3(axis_center), _vec3(axis_direction),
+                              _ptr(res.get("e3")), _ptr(res.get("evals")), _ptr(res.get("fa")),
+                              _ptr(res.get("ha")), _ptr(res.get("ia")), _ptr(res.get("flags")),
+                              _ptr(workspace), ws_bytes, _stream_handle(dev))
+    _check(code)
+    return res
+
+
+def st_angles(e3, axis_center, axis_direction, mask=None, outputs: Iterable[str] = ("ha", "ia"),
+              out: Optional[dict] = None):
+    """Helix / intrusion angles of a fibre field ``e3`` (3, nz, ny, nx) about a new axis."""
+    import torch
+    lib = load_library()
+    _require_device_tensor("e3", e3, (torch.float32,))
+    if e3.dim() != 4 or e3.shape[0] != 3:
+        raise ValueError("e3 must be (3, nz, ny, nx)")
+    _, nz, ny, nx = e3.shape
+    dev = e3.device
+    if mask is not None:
+        _require_device_tensor("mask", mask, (torch.uint8, torch.bool), (nz, ny, nx))
+        if mask.dtype == torch.bool:
+            mask = mask.view(torch.uint8)
+    res = {}
+    out = out or {}
+    for k in outputs:
+        if k not in ("ha", "ia", "flags"):
+            raise ValueError(f"unknown output {k!r}")
+        dt = torch.uint8 if k == "flags" else torch.float32
+        if k in out:
+            _require_device_tensor(k, out[k], (dt,), (nz, ny, nx))
+            res[k] = out[k]
+        else:
+            res[k] = torch.empty((nz, ny, nx), dtype=dt, device=dev)
+    with torch.cuda.device(dev):
+        code = lib.st_angles(_ptr(e3), _ptr(mask), nz, ny, nx, _vec3(axis_center), _vec3(axis_direction),
+                             _ptr(res.get("ha")), _ptr(res.get("ia")), _ptr(res.get("flags")),
+                             _stream_handle(dev))
+    _check(code)
+    return res
+
+
+def st_surrogate_infer(*args, **kwargs):
+    """The learned surrogate entry point; this build reports it as unsupported."""
+    lib = load_library()
+    code = lib.st_surrogate_infer(None, 0, None, 0, 0, 0, None, 0, 0.0, 0.0, 0.0, 0.0, None, None,
+                                  None, None, None, None, None, None)
+    _check(code)
+
+
+def profile_enable(on: bool = True):
+    _check(load_library().st_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(load_library().st_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel name: (total milliseconds, launches)} accumulated since the last reset."""
+    lib = load_library()
+    n = lib.st_profile_read(-1, None, 0, None, None)
+    if n < 0:
+        _check(-n)
+    out = {}
+    for i in range(n):
+        buf = ctypes.create_string_buffer(64)
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        lib.st_profile_read(i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt))
+        out[buf.value.decode()] = (ms.value, cnt.value)
+    return out

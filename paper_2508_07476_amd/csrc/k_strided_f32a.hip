@@ -1,0 +1,12 @@
+// Instantiations of the strided-axis correlation kernel: float input, G output, radii up to 12.
+#include "k_strided_impl.h"
+
+namespace st {
+
+hipError_t launch_strided_f32_small(int R, const StridedParams& p, hipStream_t stream) {
+#define ST_CASE(r) case r: return strided_impl::launch_r<float, false, r>(p, stream);
+  switch (R) { ST_RADII_SIGMA_SMALL(ST_CASE) default: return hipErrorInvalidValue; }
+#undef ST_CASE
+}
+
+}  // namespace st

@@ -1,0 +1,12 @@
+// Instantiations of the strided-axis correlation kernel: float input, G and D outputs.
+#include "k_strided_impl.h"
+
+namespace st {
+
+hipError_t launch_strided_f32d(int R, const StridedParams& p, hipStream_t stream) {
+#define ST_CASE(r) case r: return strided_impl::launch_r<float, true, r>(p, stream);
+  switch (R) { ST_RADII_SIGMA(ST_CASE) default: return hipErrorInvalidValue; }
+#undef ST_CASE
+}
+
+}  // namespace st

@@ -1,0 +1,84 @@
+// 1-D Gaussian / derivative-of-Gaussian correlation along a strided axis (z or y).
+//
+// Lanes of a wave own 64 consecutive x columns (coalesced loads and stores);
+// every lane walks the filtered axis with a register window of 2R+1 samples.
+// The window rotates by static register renaming: the output loop is expanded
+// (by a fold over an index sequence, so the expansion never depends on the
+// unroller's size limits) to the window length, and sample k of output j sits
+// in register (j + k) mod (2R+1).  Each input sample is loaded once per chunk,
+// the axis position is wave-uniform (boundary reflection runs on the scalar
+// unit) and the taps are kernel arguments held in scalar registers.
+#pragma once
+#include <utility>
+
+#include "st_device.h"
+
+namespace st {
+namespace strided_impl {
+
+template <int R, typename Tin, bool WITH_D>
+__global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
+  constexpr int W = 2 * R + 1;
+  const int lane = threadIdx.x;  // 0..63, x within the tile
+  // flattened block index: x tile fastest, then "other" tile, then chunk, then job
+  int64_t b = blockIdx.x;
+  const int64_t xt = b % p.x_tiles;
+  b /= p.x_tiles;
+  const int64_t ot = b % p.o_tiles;
+  b /= p.o_tiles;
+  const int chunk_id = static_cast<int>(b % p.nchunks);
+  const int job = static_cast<int>(b / p.nchunks);
+
+  const int64_t o = ot * 4 + threadIdx.y;
+  if (o >= p.n_other) return;  // wave-uniform
+  const int64_t x0 = xt * 64;
+  const bool active = x0 + lane < p.nx;
+  const int lx = active ? lane : static_cast<int>(p.nx - 1 - x0);  // keep loads in range
+
+  const Tin* in = static_cast<const Tin*>(p.job[job].in) + o * p.s_other + x0;
+  float* og = p.job[job].out_g + o * p.s_other + x0;
+  float* od = WITH_D ? p.job[job].out_d + o * p.s_other + x0 : nullptr;
+
+  const int64_t n = p.n_axis;
+  const int64_t a0 = static_cast<int64_t>(chunk_id) * p.chunk;
+  const int64_t len = (n - a0) < p.chunk ? (n - a0) : p.chunk;
+
+  float win[W];
+#pragma unroll
+  for (int j = 0; j < 2 * R; ++j) win[j] = load_as_float(in + reflect(a0 - R + j, n) * p.s_axis + lx);
+
+  for (int64_t tb = 0; tb < len; tb += W) {
+    auto step = [&]<int J>(std::integral_constant<int, J>) {
+      const int64_t t = tb + J;
+      // newest sample of output t (index a0 + t + R); reflection keeps it in range
+      win[(J + 2 * R) % W] = load_as_float(in + reflect(a0 + t + R, n) * p.s_axis + lx);
+      if (t < len) {
+        float g = 0.f, d = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const float v = win[(J + k) % W];
+          g = fmaf(p.wg.w[k], v, g);
+          if constexpr (WITH_D) d = fmaf(p.wd.w[k], v, d);
+        }
+        if (active) {
+          og[(a0 + t) * p.s_axis + lane] = g;
+          if constexpr (WITH_D) od[(a0 + t) * p.s_axis + lane] = d;
+        }
+      }
+    };
+    [&]<int... J>(std::integer_sequence<int, J...>) {
+      (step(std::integral_constant<int, J>{}), ...);
+    }(std::make_integer_sequence<int, W>{});
+  }
+}
+
+template <typename Tin, bool WITH_D, int R>
+hipError_t launch_r(const StridedParams& p, hipStream_t stream) {
+  const int64_t blocks = p.x_tiles * p.o_tiles * p.nchunks * p.njobs;
+  hipLaunchKernelGGL((k_strided<R, Tin, WITH_D>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4),
+                     0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace strided_impl
+}  // namespace st

@@ -1,0 +1,459 @@
+// C ABI of the structure-tensor library: argument validation, workspace plan,
+// filter taps, kernel sequence on the caller's stream, and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "st_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int device_fail(hipError_t e, const char* what) {
+  return fail(ST_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int radius_of(double scale, double truncate) {
+  if (!finite_pos(scale) || !finite_pos(truncate)) return -1;
+  const double r = std::floor(truncate * scale + 0.5);
+  if (r > 1e6) return 1 << 20;
+  return static_cast<int>(r);
+}
+
+// Normalised sampled Gaussian (w0) and derivative (w1 = k/s^2 w0) taps of
+// radius R, computed in double and rounded to float, stored centred in a
+// window of radius Rpad >= R (the outer taps are exact zeros).
+void make_taps(double s, int R, int Rpad, st::Taps& w0, st::Taps* w1) {
+  double g[st::kMaxTaps];
+  double sum = 0.0;
+  for (int k = -R; k <= R; ++k) {
+    g[k + R] = std::exp(-(double(k) * k) / (2.0 * s * s));
+    sum += g[k + R];
+  }
+  std::memset(&w0, 0, sizeof(w0));
+  if (w1) std::memset(w1, 0, sizeof(*w1));
+  for (int k = -R; k <= R; ++k) {
+    const double v = g[k + R] / sum;
+    w0.w[k + Rpad] = static_cast<float>(v);
+    if (w1) w1->w[k + Rpad] = static_cast<float>((double(k) / (s * s)) * v);
+  }
+}
+
+bool checked_count(int64_t nz, int64_t ny, int64_t nx, int64_t* n) {
+  if (nz < 1 || ny < 1 || nx < 1) return false;
+  if (nz > INT32_MAX || ny > INT32_MAX || nx > INT32_MAX) return false;
+  int64_t a;
+  if (__builtin_mul_overflow(nz, ny, &a)) return false;
+  if (__builtin_mul_overflow(a, nx, n)) return false;
+  // every byte count derived from n (12 float planes) must fit
+  size_t b;
+  if (__builtin_mul_overflow(static_cast<size_t>(*n), size_t(48), &b)) return false;
+  return true;
+}
+
+size_t plane_bytes(int64_t n) { return ((static_cast<size_t>(n) * 4 + 255) / 256) * 256; }
+
+// The buffer [p, p + bytes) must lie inside one device allocation.
+int check_buffer(const void* p, size_t bytes, const char* name) {
+  if (p == nullptr) return ST_OK;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  hipError_t e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+  if (e != hipSuccess || base == nullptr) {
+    (void)hipGetLastError();
+    return fail(ST_ERR_INVALID_ARG, "%s is not a device allocation (%s)", name, hipGetErrorString(e));
+  }
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t hi = lo + size;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  if (a < lo || a + bytes > hi || a + bytes < a)
+    return fail(ST_ERR_INVALID_ARG, "%s: %zu bytes needed past its address but the allocation ends sooner",
+                name, bytes);
+  return ST_OK;
+}
+
+int check_axis(const double* c, const double* d, double unit[3]) {
+  if ((c == nullptr) != (d == nullptr))
+    return fail(ST_ERR_INVALID_ARG, "axis_center and axis_direction must both be given or both be NULL");
+  if (c == nullptr) return ST_OK;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(c[i]) || !std::isfinite(d[i]))
+      return fail(ST_ERR_INVALID_ARG, "axis_center / axis_direction must be finite");
+  const double len = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (!(len > 0.0) || !std::isfinite(len))
+    return fail(ST_ERR_INVALID_ARG, "axis_direction must have a non-zero finite length");
+  for (int i = 0; i < 3; ++i) unit[i] = d[i] / len;
+  return ST_OK;
+}
+
+// ---- kernel timing ----------------------------------------------------------
+struct ProfEntry {
+  std::string name;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+};
+struct ProfPending {
+  int entry;
+  hipEvent_t start, stop;
+};
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfEntry> entries;
+  std::vector<ProfPending> pending;
+  std::vector<hipEvent_t> pool;
+};
+Profiler& prof() {
+  static Profiler* p = new Profiler();  // intentionally leaked: used until process exit
+  return *p;
+}
+
+hipEvent_t take_event() {
+  Profiler& P = prof();
+  if (!P.pool.empty()) {
+    hipEvent_t e = P.pool.back();
+    P.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` on `stream`, bracketed by timing events when profiling is on.
+template <class F>
+hipError_t timed(const char* name, hipStream_t stream, F&& fn) {
+  Profiler& P = prof();
+  if (!P.on) return fn();
+  std::lock_guard<std::mutex> lk(P.mu);
+  int idx = -1;
+  for (size_t i = 0; i < P.entries.size(); ++i)
+    if (P.entries[i].name == name) idx = static_cast<int>(i);
+  if (idx < 0) {
+    P.entries.push_back(ProfEntry{name, 0.0, 0});
+    idx = static_cast<int>(P.entries.size()) - 1;
+  }
+  hipEvent_t a = take_event(), b = take_event();
+  if (a == nullptr || b == nullptr) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, stream);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, stream);
+  if (e != hipSuccess) return e;
+  P.pending.push_back(ProfPending{idx, a, b});
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int st_version(void) { return 10000; }
+
+const char* st_last_error(void) { return g_error.c_str(); }
+
+int st_filter_radius(double scale, double truncate) { return radius_of(scale, truncate); }
+
+size_t st_workspace_bytes(int64_t nz, int64_t ny, int64_t nx) {
+  int64_t n;
+  if (!checked_count(nz, ny, nx, &n)) return 0;
+  return 12 * plane_bytes(n);
+}
+
+int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, int64_t ny,
+               int64_t nx, double sigma, double rho, double truncate, const double* axis_center,
+               const double* axis_direction, float* e3, float* evals, float* fa, float* ha,
+               float* ia, uint8_t* flags, void* workspace, size_t workspace_bytes, void* stream_) {
+  g_error.clear();
+  // ---- host-only validation (no HIP call before it passes) ----
+  if (volume == nullptr) return fail(ST_ERR_INVALID_ARG, "volume is NULL");
+  if (dtype != ST_DTYPE_U16 && dtype != ST_DTYPE_F32)
+    return fail(ST_ERR_INVALID_ARG, "dtype %d is neither ST_DTYPE_U16 nor ST_DTYPE_F32", dtype);
+  int64_t n;
+  if (!checked_count(nz, ny, nx, &n))
+    return fail(ST_ERR_INVALID_ARG, "sizes (%lld, %lld, %lld) must be >= 1, < 2^31 each, and their byte counts must fit",
+                (long long)nz, (long long)ny, (long long)nx);
+  if (!finite_pos(sigma) || !finite_pos(rho) || !finite_pos(truncate))
+    return fail(ST_ERR_INVALID_ARG, "sigma, rho and truncate must be finite and > 0");
+  const int rs = radius_of(sigma, truncate), rr = radius_of(rho, truncate);
+  if (rs < 1 || rr < 1)
+    return fail(ST_ERR_INVALID_ARG, "kernel radius floor(truncate*scale + 0.5) must be >= 1 (got %d, %d)", rs, rr);
+  if (rs > ST_MAX_RADIUS_SIGMA || rr > ST_MAX_RADIUS_RHO)
+    return fail(ST_ERR_UNSUPPORTED, "kernel radius %d (sigma) / %d (rho) exceeds %d / %d", rs, rr,
+                ST_MAX_RADIUS_SIGMA, ST_MAX_RADIUS_RHO);
+  double unit[3] = {0, 0, 0};
+  int st = check_axis(axis_center, axis_direction, unit);
+  if (st != ST_OK) return st;
+  const bool has_axis = axis_center != nullptr;
+  if (!has_axis && (ha != nullptr || ia != nullptr))
+    return fail(ST_ERR_INVALID_ARG, "ha / ia need an axis (axis_center and axis_direction)");
+  if (!e3 && !evals && !fa && !ha && !ia && !flags)
+    return fail(ST_ERR_INVALID_ARG, "no output requested");
+  const size_t ws_need = 12 * plane_bytes(n);
+  if (workspace == nullptr && workspace_bytes != 0)
+    return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
+  if (workspace != nullptr && workspace_bytes < ws_need)
+    return fail(ST_ERR_INVALID_ARG, "workspace_bytes %zu < required %zu", workspace_bytes, ws_need);
+
+  // ---- device buffer checks ----
+  const size_t N = static_cast<size_t>(n);
+  const size_t esz = dtype == ST_DTYPE_U16 ? 2 : 4;
+  if ((st = check_buffer(volume, N * esz, "volume")) != ST_OK) return st;
+  if ((st = check_buffer(mask, N, "mask")) != ST_OK) return st;
+  if ((st = check_buffer(e3, 3 * N * 4, "e3")) != ST_OK) return st;
+  if ((st = check_buffer(evals, 3 * N * 4, "evals")) != ST_OK) return st;
+  if ((st = check_buffer(fa, N * 4, "fa")) != ST_OK) return st;
+  if ((st = check_buffer(ha, N * 4, "ha")) != ST_OK) return st;
+  if ((st = check_buffer(ia, N * 4, "ia")) != ST_OK) return st;
+  if ((st = check_buffer(flags, N, "flags")) != ST_OK) return st;
+  if ((st = check_buffer(workspace, ws_need, "workspace")) != ST_OK) return st;
+  if ((reinterpret_cast<uintptr_t>(volume) % esz) != 0)
+    return fail(ST_ERR_INVALID_ARG, "volume is not aligned to its element size");
+  for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
+                        static_cast<const void*>(fa), static_cast<const void*>(ha),
+                        static_cast<const void*>(ia)})
+    if (q && (reinterpret_cast<uintptr_t>(q) % 4) != 0)
+      return fail(ST_ERR_INVALID_ARG, "float outputs must be 4-byte aligned");
+
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  bool owned = false;
+  if (ws == nullptr) {
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), ws_need, stream);
+    if (e != hipSuccess || ws == nullptr) {
+      (void)hipGetLastError();
+      return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) failed: %s", ws_need, hipGetErrorString(e));
+    }
+    owned = true;
+  }
+  const size_t pb = plane_bytes(n);
+  float* A[6];
+  float* B[6];
+  for (int c = 0; c < 6; ++c) {
+    A[c] = reinterpret_cast<float*>(ws + c * pb);
+    B[c] = reinterpret_cast<float*>(ws + (6 + c) * pb);
+  }
+
+  // compiled radii: the next one up, taps zero-padded
+  const int ps = st::padded_radius(rs, true), pr = st::padded_radius(rr, false);
+  st::Taps gs, ds, gr;
+  make_taps(sigma, rs, ps, gs, &ds);
+  make_taps(rho, rr, pr, gr, nullptr);
+
+  auto strided = [&](bool zaxis, int njobs, const st::StridedJob* jobs, int R, int in_dtype,
+                     bool with_d, const st::Taps& wg, const st::Taps* wd) {
+    st::StridedParams p;
+    std::memset(&p, 0, sizeof(p));
+    for (int j = 0; j < njobs; ++j) p.job[j] = jobs[j];
+    p.njobs = njobs;
+    p.nx = nx;
+    if (zaxis) {
+      p.n_axis = nz; p.s_axis = ny * nx; p.n_other = ny; p.s_other = nx;
+    } else {
+      p.n_axis = ny; p.s_axis = nx; p.n_other = nz; p.s_other = ny * nx;
+    }
+    p.x_tiles = (nx + 63) / 64;
+    p.o_tiles = (p.n_other + 3) / 4;
+    // split the filtered axis until the launch has enough waves to fill the chip
+    const int64_t waves = p.x_tiles * p.n_other * njobs;
+    int nchunks = 1;
+    const int64_t min_chunk = std::max<int64_t>(64, 4 * R);
+    while (waves * nchunks < 16384 && (p.n_axis + 2 * nchunks - 1) / (2 * nchunks) >= min_chunk)
+      nchunks *= 2;
+    p.nchunks = nchunks;
+    p.chunk = (p.n_axis + nchunks - 1) / nchunks;
+    p.nchunks = static_cast<int>((p.n_axis + p.chunk - 1) / p.chunk);
+    p.wg = wg;
+    if (wd) p.wd = *wd;
+    return st::launch_strided(R, in_dtype, with_d, p, stream);
+  };
+
+  hipError_t e = hipSuccess;
+  const char* stage = "";
+  do {
+    // gradient: z pass (G, D), y pass, x pass + outer product
+    {
+      st::StridedJob j = {volume, B[0], B[1]};
+      stage = "grad_z";
+      e = timed("grad_z", stream, [&] { return strided(true, 1, &j, ps, dtype, true, gs, &ds); });
+      if (e != hipSuccess) break;
+    }
+    {
+      st::StridedJob j0 = {B[0], A[0], A[1]};
+      stage = "grad_y";
+      e = timed("grad_y", stream, [&] { return strided(false, 1, &j0, ps, ST_DTYPE_F32, true, gs, &ds); });
+      if (e != hipSuccess) break;
+      st::StridedJob j1 = {B[1], A[2], nullptr};
+      e = timed("grad_y", stream, [&] { return strided(false, 1, &j1, ps, ST_DTYPE_F32, false, gs, nullptr); });
+      if (e != hipSuccess) break;
+    }
+    {
+      st::XGradParams p;
+      std::memset(&p, 0, sizeof(p));
+      p.gg = A[0]; p.dg = A[1]; p.gd = A[2];
+      for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
+      p.nx = nx; p.nrows = nz * ny; p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
+      p.vec_ok = (nx % 4) == 0;
+      p.wg = gs; p.wd = ds;
+      stage = "grad_x_outer";
+      e = timed("grad_x_outer", stream, [&] { return st::launch_xgrad(ps, p, stream); });
+      if (e != hipSuccess) break;
+    }
+    // integration: z pass, y pass (6 components each)
+    {
+      st::StridedJob j[6];
+      for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{B[c], A[c], nullptr};
+      stage = "integrate_z";
+      e = timed("integrate_z", stream, [&] { return strided(true, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
+      if (e != hipSuccess) break;
+      for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{A[c], B[c], nullptr};
+      stage = "integrate_y";
+      e = timed("integrate_y", stream, [&] { return strided(false, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
+      if (e != hipSuccess) break;
+    }
+    // x integration fused with eigen, FA, angles
+    {
+      st::XFinalParams p;
+      std::memset(&p, 0, sizeof(p));
+      for (int c = 0; c < 6; ++c) p.s[c] = B[c];
+      p.mask = mask; p.e3 = e3; p.evals = evals; p.fa = fa; p.ha = ha; p.ia = ia; p.flags = flags;
+      p.n = n; p.nz = nz; p.ny = ny; p.nx = nx; p.nrows = nz * ny;
+      p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
+      bool vec = (nx % 4) == 0;
+      for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
+                            static_cast<const void*>(fa), static_cast<const void*>(ha),
+                            static_cast<const void*>(ia)})
+        if (q && (reinterpret_cast<uintptr_t>(q) % 16) != 0) vec = false;
+      if (flags && (reinterpret_cast<uintptr_t>(flags) % 4) != 0) vec = false;
+      p.vec_ok = vec;
+      p.has_axis = has_axis;
+      if (has_axis)
+        for (int i = 0; i < 3; ++i) { p.center[i] = axis_center[i]; p.dir[i] = unit[i]; }
+      p.w = gr;
+      stage = "integrate_x_eigen";
+      e = timed("integrate_x_eigen", stream, [&] { return st::launch_xfinal(pr, p, stream); });
+      if (e != hipSuccess) break;
+    }
+  } while (false);
+
+  if (owned) {
+    hipError_t f = hipFreeAsync(ws, stream);
+    if (e == hipSuccess && f != hipSuccess) { e = f; stage = "hipFreeAsync"; }
+  }
+  if (e != hipSuccess) return device_fail(e, stage);
+  return ST_OK;
+}
+
+int st_angles(const float* e3, const uint8_t* mask, int64_t nz, int64_t ny, int64_t nx,
+              const double* axis_center, const double* axis_direction, float* ha, float* ia,
+              uint8_t* flags, void* stream_) {
+  g_error.clear();
+  if (e3 == nullptr) return fail(ST_ERR_INVALID_ARG, "e3 is NULL");
+  int64_t n;
+  if (!checked_count(nz, ny, nx, &n))
+    return fail(ST_ERR_INVALID_ARG, "sizes (%lld, %lld, %lld) must be >= 1, < 2^31 each, and their byte counts must fit",
+                (long long)nz, (long long)ny, (long long)nx);
+  if (axis_center == nullptr || axis_direction == nullptr)
+    return fail(ST_ERR_INVALID_ARG, "st_angles needs axis_center and axis_direction");
+  double unit[3];
+  int st = check_axis(axis_center, axis_direction, unit);
+  if (st != ST_OK) return st;
+  if (!ha && !ia && !flags) return fail(ST_ERR_INVALID_ARG, "no output requested");
+  const size_t N = static_cast<size_t>(n);
+  if ((st = check_buffer(e3, 3 * N * 4, "e3")) != ST_OK) return st;
+  if ((st = check_buffer(mask, N, "mask")) != ST_OK) return st;
+  if ((st = check_buffer(ha, N * 4, "ha")) != ST_OK) return st;
+  if ((st = check_buffer(ia, N * 4, "ia")) != ST_OK) return st;
+  if ((st = check_buffer(flags, N, "flags")) != ST_OK) return st;
+  for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(ha), static_cast<const void*>(ia)})
+    if (q && (reinterpret_cast<uintptr_t>(q) % 4) != 0)
+      return fail(ST_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
+
+  st::AnglesParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.e3 = e3; p.mask = mask; p.ha = ha; p.ia = ia; p.flags = flags;
+  p.n = n; p.ny = ny; p.nx = nx; p.nrows = nz * ny;
+  p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
+  p.vec_ok = 0;
+  for (int i = 0; i < 3; ++i) { p.center[i] = axis_center[i]; p.dir[i] = unit[i]; }
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  hipError_t e = timed("angles", stream, [&] { return st::launch_angles(p, stream); });
+  if (e != hipSuccess) return device_fail(e, "angles");
+  return ST_OK;
+}
+
+int st_surrogate_infer(const void*, int, const uint8_t*, int64_t, int64_t, int64_t, const void*,
+                       size_t, double, double, double, double, const double*, const double*,
+                       float*, float*, float*, float*, float*, void*) {
+  return fail(ST_ERR_UNSUPPORTED, "the learned surrogate is not part of this build");
+}
+
+int st_profile_enable(int on) {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.on = on != 0;
+  return ST_OK;
+}
+
+int st_profile_reset(void) {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (auto& q : P.pending) {
+    (void)hipEventSynchronize(q.stop);
+    P.pool.push_back(q.start);
+    P.pool.push_back(q.stop);
+  }
+  P.pending.clear();
+  P.entries.clear();
+  return ST_OK;
+}
+
+int st_profile_read(int index, char* name, size_t name_len, double* total_ms, int64_t* launches) {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (auto& q : P.pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(q.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, q.start, q.stop);
+    if (e != hipSuccess) return -device_fail(e, "st_profile_read");
+    P.entries[q.entry].total_ms += ms;
+    P.entries[q.entry].launches += 1;
+    P.pool.push_back(q.start);
+    P.pool.push_back(q.stop);
+  }
+  P.pending.clear();
+  const int count = static_cast<int>(P.entries.size());
+  if (index >= 0 && index < count) {
+    const ProfEntry& en = P.entries[index];
+    if (name && name_len) {
+      std::strncpy(name, en.name.c_str(), name_len - 1);
+      name[name_len - 1] = '\0';
+    }
+    if (total_ms) *total_ms = en.total_ms;
+    if (launches) *launches = en.launches;
+  }
+  return count;
+}
+
+}  // extern "C"

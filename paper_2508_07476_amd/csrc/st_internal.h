@@ -1,0 +1,127 @@
+// Internal declarations shared by the host layer and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/st.h"
+
+namespace st {
+
+constexpr int kMaxTaps = 2 * ST_MAX_RADIUS_RHO + 1;
+
+// Kernel radii compiled into the library.  A request for radius R runs the
+// smallest compiled radius R' >= R with the taps zero-padded to 2R'+1: the
+// extra terms are exact zeros, so the result equals the radius-R filter.
+#define ST_RADII_SIGMA_SMALL(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12)
+#define ST_RADII_SIGMA(X) ST_RADII_SIGMA_SMALL(X) X(14) X(16)
+#define ST_RADII_LARGE(X) X(14) X(16) X(20) X(24) X(28) X(32)
+#define ST_RADII_RHO(X) ST_RADII_SIGMA(X) X(20) X(24) X(28) X(32)
+
+inline int padded_radius(int R, bool sigma) {
+  static const int rs[] = {
+#define ST_LIST(r) r,
+      ST_RADII_SIGMA(ST_LIST)
+  };
+  static const int rr[] = {ST_RADII_RHO(ST_LIST)
+#undef ST_LIST
+  };
+  const int* b = sigma ? rs : rr;
+  const int cnt = sigma ? int(sizeof(rs) / sizeof(int)) : int(sizeof(rr) / sizeof(int));
+  for (int i = 0; i < cnt; ++i)
+    if (b[i] >= R) return b[i];
+  return -1;
+}
+
+// Filter taps in float32, index m <-> offset k = m - R.  Passed by value as a
+// kernel argument so every tap lives in a scalar register.
+struct Taps {
+  float w[kMaxTaps];
+};
+
+// ---- strided-axis correlation (z or y) -------------------------------------
+// One job = one input plane set filtered into one or two outputs (G and, when
+// out_d != nullptr, D) with the same register window.
+struct StridedJob {
+  const void* in;
+  float* out_g;
+  float* out_d;
+};
+
+struct StridedParams {
+  StridedJob job[6];
+  int njobs;
+  int nchunks;       // chunks along the filtered axis
+  int64_t chunk;     // outputs per chunk along the filtered axis
+  int64_t n_axis;    // length of the filtered axis
+  int64_t s_axis;    // element stride of the filtered axis
+  int64_t n_other;   // length of the remaining non-x axis
+  int64_t s_other;   // its element stride
+  int64_t nx;
+  int64_t x_tiles;   // ceil(nx / 64)
+  int64_t o_tiles;   // ceil(n_other / 4)
+  Taps wg;
+  Taps wd;
+};
+
+// in_dtype: ST_DTYPE_U16 or ST_DTYPE_F32.  with_d selects the two-output variant.
+hipError_t launch_strided(int R, int in_dtype, bool with_d, const StridedParams& p,
+                          hipStream_t stream);
+
+// ---- x-axis gradient pass fused with the outer product ----------------------
+struct XGradParams {
+  const float* gg;  // Gy Gz V  -> Dx gives g_x
+  const float* dg;  // Dy Gz V  -> Gx gives g_y
+  const float* gd;  // Gy Dz V  -> Gx gives g_z
+  float* prod[6];   // zz, zy, zx, yy, yx, xx
+  int64_t nx;
+  int64_t nrows;    // nz * ny
+  int64_t x_tiles;  // ceil(nx / kXTile)
+  int vec_ok;       // nx % 4 == 0 and every output 16-byte aligned: float4 stores
+  Taps wg;
+  Taps wd;
+};
+
+// ---- x-axis integration fused with eigen-decomposition, FA and angles ------
+struct XFinalParams {
+  const float* s[6];  // z- and y-integrated products, (zz, zy, zx, yy, yx, xx)
+  const uint8_t* mask;
+  float* e3;          // [3][N] or null
+  float* evals;       // [3][N] or null
+  float* fa;
+  float* ha;
+  float* ia;
+  uint8_t* flags;
+  int64_t n;          // nz * ny * nx
+  int64_t nz, ny, nx;
+  int64_t nrows;
+  int64_t x_tiles;
+  int vec_ok;         // nx % 4 == 0 and every output 16-byte aligned (flags 4-byte)
+  int has_axis;
+  double center[3];   // (z, y, x)
+  double dir[3];      // unit (z, y, x)
+  Taps w;
+};
+
+constexpr int kXVec = 4;                 // consecutive x outputs per lane
+constexpr int kXTile = 64 * kXVec;       // x outputs per wave
+constexpr int kRowsPerBlock = 4;         // one row per wave, 4 waves per block
+
+hipError_t launch_xgrad(int R, const XGradParams& p, hipStream_t stream);
+hipError_t launch_xfinal(int R, const XFinalParams& p, hipStream_t stream);
+
+// ---- standalone angles ------------------------------------------------------
+struct AnglesParams {
+  const float* e3;
+  const uint8_t* mask;
+  float* ha;
+  float* ia;
+  uint8_t* flags;
+  int64_t n, ny, nx, nrows, x_tiles;
+  int vec_ok;
+  double center[3];
+  double dir[3];
+};
+hipError_t launch_angles(const AnglesParams& p, hipStream_t stream);
+
+}  // namespace st

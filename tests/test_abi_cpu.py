@@ -1,0 +1,115 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every symbol
+the header declares, and rejects invalid arguments on the host before any HIP
+call (fake non-null pointers are safe because validation fails first)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2508_07476_amd as st
+from paper_2508_07476_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "st.h")
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: every call below fails validation first
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2508_07476_amd.csrc import build
+        build.build()
+    return st.load_library()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(st_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"st_compute", "st_angles", "st_surrogate_infer"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in B.SIGNATURES, n
+    assert set(B.SIGNATURES) == set(names)
+
+
+def test_version_radius_and_workspace(lib):
+    assert lib.st_version() >= 10000
+    assert [lib.st_filter_radius(s, 4.0) for s in (1.0, 1.5, 2.0, 3.0, 4.0, 6.0)] == [4, 6, 8, 12, 16, 24]
+    assert lib.st_filter_radius(0.0, 4.0) == -1 and lib.st_filter_radius(1.0, float("nan")) == -1
+    n = 5 * 7 * 9
+    plane = ((n * 4 + 255) // 256) * 256
+    assert lib.st_workspace_bytes(5, 7, 9) == 12 * plane
+    assert lib.st_workspace_bytes(0, 7, 9) == 0
+    assert lib.st_workspace_bytes(2 ** 31, 1, 1) == 0          # each size < 2^31
+    assert lib.st_workspace_bytes(2 ** 30, 2 ** 30, 2 ** 30) == 0  # product overflow
+
+
+def _compute(lib, **kw):
+    a = dict(volume=FAKE, dtype=B.ST_DTYPE_U16, mask=None, nz=8, ny=8, nx=8, sigma=1.0, rho=2.0,
+             truncate=4.0, center=None, direction=None, e3=FAKE, evals=None, fa=None, ha=None, ia=None,
+             flags=None, ws=None, ws_bytes=0)
+    a.update(kw)
+    vec = lambda v: None if v is None else (ctypes.c_double * 3)(*v)  # noqa: E731
+    code = lib.st_compute(a["volume"], a["dtype"], a["mask"], a["nz"], a["ny"], a["nx"], a["sigma"],
+                          a["rho"], a["truncate"], vec(a["center"]), vec(a["direction"]), a["e3"],
+                          a["evals"], a["fa"], a["ha"], a["ia"], a["flags"], a["ws"], a["ws_bytes"], None)
+    return code, lib.st_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code,text", [
+    (dict(volume=None), B.ST_ERR_INVALID_ARG, "volume is NULL"),
+    (dict(dtype=7), B.ST_ERR_INVALID_ARG, "dtype"),
+    (dict(nz=0), B.ST_ERR_INVALID_ARG, "sizes"),
+    (dict(nx=-3), B.ST_ERR_INVALID_ARG, "sizes"),
+    (dict(nz=2 ** 31), B.ST_ERR_INVALID_ARG, "sizes"),
+    (dict(nz=2 ** 30, ny=2 ** 30, nx=2 ** 30), B.ST_ERR_INVALID_ARG, "sizes"),
+    (dict(sigma=0.0), B.ST_ERR_INVALID_ARG, "sigma"),
+    (dict(rho=float("nan")), B.ST_ERR_INVALID_ARG, "sigma"),
+    (dict(truncate=-1.0), B.ST_ERR_INVALID_ARG, "sigma"),
+    (dict(sigma=0.1), B.ST_ERR_INVALID_ARG, "radius"),
+    (dict(sigma=5.0), B.ST_ERR_UNSUPPORTED, "exceeds"),
+    (dict(rho=8.2), B.ST_ERR_UNSUPPORTED, "exceeds"),
+    (dict(center=(1, 2, 3)), B.ST_ERR_INVALID_ARG, "both"),
+    (dict(center=(1, 2, 3), direction=(0, 0, 0)), B.ST_ERR_INVALID_ARG, "non-zero"),
+    (dict(center=(1, float("inf"), 3), direction=(1, 0, 0)), B.ST_ERR_INVALID_ARG, "finite"),
+    (dict(ha=FAKE), B.ST_ERR_INVALID_ARG, "need an axis"),
+    (dict(e3=None), B.ST_ERR_INVALID_ARG, "no output"),
+    (dict(ws=None, ws_bytes=64), B.ST_ERR_INVALID_ARG, "workspace is NULL"),
+    (dict(ws=FAKE, ws_bytes=64), B.ST_ERR_INVALID_ARG, "workspace_bytes"),
+])
+def test_compute_rejects_invalid_arguments_on_host(lib, kw, code, text):
+    got, msg = _compute(lib, **kw)
+    assert got == code, msg
+    assert text in msg
+
+
+def test_angles_rejects_invalid_arguments_on_host(lib):
+    c = (ctypes.c_double * 3)(1, 2, 3)
+    d = (ctypes.c_double * 3)(1, 0, 0)
+    z = (ctypes.c_double * 3)(0, 0, 0)
+    assert lib.st_angles(None, None, 4, 4, 4, c, d, FAKE, FAKE, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_angles(FAKE, None, 4, 4, 4, None, None, FAKE, FAKE, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_angles(FAKE, None, 4, 4, 4, c, z, FAKE, FAKE, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_angles(FAKE, None, 4, 0, 4, c, d, FAKE, FAKE, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_angles(FAKE, None, 4, 4, 4, c, d, None, None, None, None) == B.ST_ERR_INVALID_ARG
+    assert "no output" in lib.st_last_error().decode()
+
+
+def test_surrogate_is_reported_unsupported(lib):
+    with pytest.raises(st.StError) as e:
+        st.st_surrogate_infer()
+    assert e.value.code == B.ST_ERR_UNSUPPORTED
+
+
+def test_error_message_is_per_call(lib):
+    _compute(lib, dtype=9)
+    assert "dtype" in lib.st_last_error().decode()
+    _compute(lib, nz=0)
+    assert "dtype" not in lib.st_last_error().decode()
