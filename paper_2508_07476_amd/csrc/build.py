@@ -19,8 +19,17 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libst.so")
-SOURCES = ["st_api.hip", "k_strided.hip", "k_strided_u16.hip", "k_strided_f32d.hip", "k_strided_f32a.hip",
-           "k_strided_f32b.hip", "k_xpass.hip", "k_xgrad.hip", "k_xfinala.hip", "k_xfinalb.hip", "k_angles.hip"]
+# (source, extra defines, object name); the strided instantiations are split into
+# groups so that the largest radii compile in parallel
+STRIDED_GROUPS = 8
+UNITS = ([("st_api.hip", [], "st_api"), ("k_strided.hip", [], "k_strided"),
+          ("k_xpass.hip", [], "k_xpass"), ("k_xgrad.hip", [], "k_xgrad"),
+          ("k_xfinala.hip", [], "k_xfinala"), ("k_xfinalb.hip", [], "k_xfinalb"),
+          ("k_angles.hip", [], "k_angles")] +
+         [("k_strided_inst.hip", [f"-DST_STRIDED_GROUP={g}"], f"k_strided_g{g}")
+          for g in range(STRIDED_GROUPS)])
+# most expensive first, so they do not finish last
+COST = {"k_strided_g7": 9, "k_strided_g6": 8, "k_strided_g5": 7, "k_strided_g4": 6, "k_strided_g3": 5}
 ARCH = "gfx950"
 
 CFLAGS = [
@@ -38,9 +47,10 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *CFLAGS, "-c", os.path.join(HERE, src), "-o", obj]
+def _compile(unit):
+    src, defs, name = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc(), *CFLAGS, *defs, "-c", os.path.join(HERE, src), "-o", obj]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -50,9 +60,8 @@ def _compile(src):
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
-    # the largest translation units first, so they do not finish last
-    order = sorted(SOURCES, key=lambda f: -os.path.getsize(os.path.join(HERE, f)))
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 4, 16)
+    order = sorted(UNITS, key=lambda u: -COST.get(u[2], 0))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_compile, order))
     objs = [o for o, _, _ in results]

@@ -6,8 +6,9 @@
 // (by a fold over an index sequence, so the expansion never depends on the
 // unroller's size limits) to the window length, and sample k of output j sits
 // in register (j + k) mod (2R+1).  Each input sample is loaded once per chunk,
-// the axis position is wave-uniform (boundary reflection runs on the scalar
-// unit) and the taps are kernel arguments held in scalar registers.
+// one block of 2R+1 outputs ahead of its use, so every lane keeps 2R+1 loads
+// in flight; the axis position is wave-uniform (boundary reflection runs on
+// the scalar unit) and the taps are kernel arguments held in scalar registers.
 #pragma once
 #include <utility>
 
@@ -40,29 +41,38 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   float* od = WITH_D ? p.job[job].out_d + o * p.s_other + x0 : nullptr;
 
   const int64_t n = p.n_axis;
+  const int64_t sa = p.s_axis;
   const int64_t a0 = static_cast<int64_t>(chunk_id) * p.chunk;
   const int64_t len = (n - a0) < p.chunk ? (n - a0) : p.chunk;
+  // relative sample i <-> axis index a0 - R + i (reflected into [0, n))
+  auto sample = [&](int64_t i) { return load_as_float(in + reflect(a0 - R + i, n) * sa + lx); };
 
-  float win[W];
+  // win: the 2R+1 samples of the current output; pre: the newest sample of each
+  // output of the current block of W outputs, loaded one block ahead so that W
+  // loads per lane are always in flight.
+  float win[W], pre[W];
 #pragma unroll
-  for (int j = 0; j < 2 * R; ++j) win[j] = load_as_float(in + reflect(a0 - R + j, n) * p.s_axis + lx);
+  for (int j = 0; j < 2 * R; ++j) win[j] = sample(j);
+#pragma unroll
+  for (int j = 0; j < W; ++j) pre[j] = sample(2 * R + j);
 
   for (int64_t tb = 0; tb < len; tb += W) {
     auto step = [&]<int J>(std::integral_constant<int, J>) {
       const int64_t t = tb + J;
-      // newest sample of output t (index a0 + t + R); reflection keeps it in range
-      win[(J + 2 * R) % W] = load_as_float(in + reflect(a0 + t + R, n) * p.s_axis + lx);
+      const float v = pre[J];
+      if (t + W < len) pre[J] = sample(t + W + 2 * R);  // same step of the next block
+      win[(J + 2 * R) % W] = v;
       if (t < len) {
         float g = 0.f, d = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const float v = win[(J + k) % W];
-          g = fmaf(p.wg.w[k], v, g);
-          if constexpr (WITH_D) d = fmaf(p.wd.w[k], v, d);
+          const float u = win[(J + k) % W];
+          g = fmaf(p.wg.w[k], u, g);
+          if constexpr (WITH_D) d = fmaf(p.wd.w[k], u, d);
         }
         if (active) {
-          og[(a0 + t) * p.s_axis + lane] = g;
-          if constexpr (WITH_D) od[(a0 + t) * p.s_axis + lane] = d;
+          og[(a0 + t) * sa + lane] = g;
+          if constexpr (WITH_D) od[(a0 + t) * sa + lane] = d;
         }
       }
     };

@@ -1,29 +1,51 @@
 // x-axis passes: the last gradient pass fused with the outer product, and the
 // last integration pass fused with the eigen-decomposition, FA and angles.
 //
-// Each wave owns one (z, y) row segment of kXTile = 256 outputs.  It stages the
-// segment plus a halo of R samples on each side in LDS (coalesced global
-// loads, boundary reflection per lane), then every lane computes kXVec = 4
-// consecutive outputs from a register copy of its 2R+4 window, read from LDS
-// with 16-byte loads, so each LDS value feeds up to 4 outputs.
+// Each block is one wave and owns one (z, y) row segment of kXTile = 256
+// outputs.  It stages the segment plus a halo of R samples on each side in LDS
+// (coalesced global loads, boundary reflection per lane only for tiles that
+// touch a face), then every lane computes kXVec = 4 consecutive outputs from a
+// register copy of its 2R+4 window, read from LDS with 16-byte loads, so each
+// LDS value feeds up to 4 outputs.
 #pragma once
 #include "st_device.h"
 
 namespace st {
 namespace xpass_impl {
 
-constexpr int lds_row(int R) { return ((kXTile + 2 * R + 4 + 3) / 4) * 4; }
+constexpr int stage_slots(int R) { return (kXTile + 2 * R + 63) / 64; }
+// LDS row length: every staging slot (64 per lane step) and the 16-byte reads
+// of the last lane's window fit.
+constexpr int lds_row(int R) {
+  return 64 * stage_slots(R) > ((kXTile + 2 * R + 4 + 3) / 4) * 4 ? 64 * stage_slots(R)
+                                                                   : ((kXTile + 2 * R + 4 + 3) / 4) * 4;
+}
 
-// Fill lds[0 .. kXTile + 2R) with row[reflect(x0 - R + i)].
+// Row index of LDS slot i = lane + 64 j (global x = x0 - R + i, reflected into
+// [0, nx)).  Slots past the staged range repeat a valid index (their values
+// are never read).  Computed once per wave and shared by every component.
 template <int R>
-__device__ __forceinline__ void stage_row(float* lds, const float* row, int64_t x0, int64_t nx,
-                                          int lane) {
+__device__ __forceinline__ void stage_index(int idx[stage_slots(R)], int64_t x0, int64_t nx, int lane) {
   const int n = static_cast<int>(nx);
+  const int g0 = static_cast<int>(x0) - R;
+  const bool interior = g0 >= 0 && g0 + 64 * stage_slots(R) <= n;  // wave-uniform
 #pragma unroll
-  for (int i = lane; i < kXTile + 2 * R; i += 64) {
-    const int gx = reflect_lane(static_cast<int>(x0) - R + i, n);
-    lds[i] = row[gx];
+  for (int j = 0; j < stage_slots(R); ++j) {
+    const int g = g0 + lane + 64 * j;
+    idx[j] = interior ? g : reflect_lane(g, n);
   }
+}
+
+// Branch-free staging: all loads of the row segment are issued before the first
+// LDS write.
+template <int R>
+__device__ __forceinline__ void stage_row(float* lds, const float* row, const int idx[stage_slots(R)],
+                                          int lane) {
+  float v[stage_slots(R)];
+#pragma unroll
+  for (int j = 0; j < stage_slots(R); ++j) v[j] = row[idx[j]];
+#pragma unroll
+  for (int j = 0; j < stage_slots(R); ++j) lds[lane + 64 * j] = v[j];
 }
 
 // out[v] = sum_k w[k] * lds[4 lane + v + k], v = 0..3
@@ -61,28 +83,26 @@ __device__ __forceinline__ void store4(float* dst, int64_t x, int64_t nx, bool v
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_xgrad(const XGradParams p) {
+__global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
   constexpr int LR = lds_row(R);
-  __shared__ __attribute__((aligned(16))) float lds[kRowsPerBlock][3][LR];
+  __shared__ __attribute__((aligned(16))) float lds[3][LR];
   const int lane = threadIdx.x;
-  const int wv = threadIdx.y;
   const int64_t xt = blockIdx.x % p.x_tiles;
-  const int64_t row = (blockIdx.x / p.x_tiles) * kRowsPerBlock + wv;
-  const bool row_ok = row < p.nrows;
-  const int64_t rr = row_ok ? row : p.nrows - 1;
+  const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
   const int64_t x0 = xt * kXTile;
-  const int64_t base = rr * p.nx;
+  const int64_t base = row * p.nx;
 
-  stage_row<R>(lds[wv][0], p.gg + base, x0, p.nx, lane);
-  stage_row<R>(lds[wv][1], p.dg + base, x0, p.nx, lane);
-  stage_row<R>(lds[wv][2], p.gd + base, x0, p.nx, lane);
+  int idx[stage_slots(R)];
+  stage_index<R>(idx, x0, p.nx, lane);
+  stage_row<R>(lds[0], p.gg + base, idx, lane);
+  stage_row<R>(lds[1], p.dg + base, idx, lane);
+  stage_row<R>(lds[2], p.gd + base, idx, lane);
   __syncthreads();
 
   float gx[kXVec], gy[kXVec], gz[kXVec];
-  conv4<R>(lds[wv][0], lane, p.wd, gx);
-  conv4<R>(lds[wv][1], lane, p.wg, gy);
-  conv4<R>(lds[wv][2], lane, p.wg, gz);
-  if (!row_ok) return;
+  conv4<R>(lds[0], lane, p.wd, gx);
+  conv4<R>(lds[1], lane, p.wg, gy);
+  conv4<R>(lds[2], lane, p.wg, gz);
 
   const int64_t x = x0 + kXVec * lane;
   if (x >= p.nx) return;
@@ -101,92 +121,82 @@ __global__ __launch_bounds__(256) void k_xgrad(const XGradParams p) {
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_xfinal(const XFinalParams p) {
+__global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
   constexpr int LR = lds_row(R);
-  __shared__ __attribute__((aligned(16))) float lds[kRowsPerBlock][6][LR];
+  __shared__ __attribute__((aligned(16))) float lds[6][LR];
   const int lane = threadIdx.x;
-  const int wv = threadIdx.y;
   const int64_t xt = blockIdx.x % p.x_tiles;
-  const int64_t row = (blockIdx.x / p.x_tiles) * kRowsPerBlock + wv;
-  const bool row_ok = row < p.nrows;
-  const int64_t rr = row_ok ? row : p.nrows - 1;
+  const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
   const int64_t x0 = xt * kXTile;
-  const int64_t base = rr * p.nx;
+  const int64_t base = row * p.nx;
 
+  {
+    int idx[stage_slots(R)];
+    stage_index<R>(idx, x0, p.nx, lane);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) stage_row<R>(lds[wv][c], p.s[c] + base, x0, p.nx, lane);
+    for (int c = 0; c < 6; ++c) stage_row<R>(lds[c], p.s[c] + base, idx, lane);
+  }
   __syncthreads();
 
-  float s[6][kXVec];
-#pragma unroll
+  // x-correlation, one component at a time (a rolled loop bounds the live
+  // window); each lane parks its 4 results in its own slots of the component's
+  // staged row, which no lane reads any more (the wave runs in lockstep).
+#pragma unroll 1
   for (int c = 0; c < 6; ++c) {
-    conv4<R>(lds[wv][c], lane, p.w, s[c]);
-    __builtin_amdgcn_sched_barrier(0);  // keep one component's window live at a time
+    float o4[kXVec];
+    conv4<R>(lds[c], lane, p.w, o4);
+    *reinterpret_cast<float4*>(&lds[c][kXVec * lane]) = make_float4(o4[0], o4[1], o4[2], o4[3]);
   }
-  if (!row_ok) return;
   const int64_t x = x0 + kXVec * lane;
   if (x >= p.nx) return;
 
-  const double pz = static_cast<double>(rr / p.ny);
-  const double py = static_cast<double>(rr % p.ny);
-  float e3[3][kXVec], ev[3][kXVec], fa[kXVec], ha[kXVec], ia[kXVec];
-  uint32_t fl[kXVec];
-#pragma unroll
+  const double pz = static_cast<double>(row / p.ny);
+  const double py = static_cast<double>(row % p.ny);
+  const int64_t n = p.n;
+#pragma unroll 1
   for (int v = 0; v < kXVec; ++v) {
-    const int64_t xv = x + v < p.nx ? x + v : p.nx - 1;
-    const bool inside = p.mask == nullptr || p.mask[base + xv] != 0;
-    if (inside) {
-      const float s6[6] = {s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], s[5][v]};
-      VoxelOut o;
-      solve_voxel(s6, p.has_axis != 0, p.center, p.dir, pz, py, static_cast<double>(x + v), o);
-      e3[0][v] = o.e3[0]; e3[1][v] = o.e3[1]; e3[2][v] = o.e3[2];
-      ev[0][v] = o.ev[0]; ev[1][v] = o.ev[1]; ev[2][v] = o.ev[2];
-      fa[v] = o.fa; ha[v] = o.ha; ia[v] = o.ia; fl[v] = o.flags;
-    } else {
-      e3[0][v] = e3[1][v] = e3[2][v] = 0.f;
-      ev[0][v] = ev[1][v] = ev[2][v] = 0.f;
-      fa[v] = ha[v] = ia[v] = 0.f;
-      fl[v] = ST_FLAG_OUTSIDE_MASK;
-    }
-  }
-  const bool vec_ok = p.vec_ok != 0;
-  if (p.e3) {
-    store4(p.e3 + base, x, p.nx, vec_ok, e3[0]);
-    store4(p.e3 + p.n + base, x, p.nx, vec_ok, e3[1]);
-    store4(p.e3 + 2 * p.n + base, x, p.nx, vec_ok, e3[2]);
-  }
-  if (p.evals) {
-    store4(p.evals + base, x, p.nx, vec_ok, ev[0]);
-    store4(p.evals + p.n + base, x, p.nx, vec_ok, ev[1]);
-    store4(p.evals + 2 * p.n + base, x, p.nx, vec_ok, ev[2]);
-  }
-  if (p.fa) store4(p.fa + base, x, p.nx, vec_ok, fa);
-  if (p.ha) store4(p.ha + base, x, p.nx, vec_ok, ha);
-  if (p.ia) store4(p.ia + base, x, p.nx, vec_ok, ia);
-  if (p.flags) {
-    if (vec_ok && x + kXVec <= p.nx) {
-      const uint32_t packed = fl[0] | (fl[1] << 8) | (fl[2] << 16) | (fl[3] << 24);
-      *reinterpret_cast<uint32_t*>(p.flags + base + x) = packed;
-    } else {
-      for (int v = 0; v < kXVec; ++v)
-        if (x + v < p.nx) p.flags[base + x + v] = static_cast<uint8_t>(fl[v]);
+    const int64_t xv = x + v;
+    if (xv < p.nx) {
+      const int64_t i = base + xv;
+      const bool inside = p.mask == nullptr || p.mask[i] != 0;
+      float e0 = 0.f, e1 = 0.f, e2 = 0.f, l1 = 0.f, l2 = 0.f, l3 = 0.f, fa = 0.f, ha = 0.f, ia = 0.f;
+      uint32_t fl = ST_FLAG_OUTSIDE_MASK;
+      if (inside) {
+        float s6[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s6[c] = lds[c][kXVec * lane + v];
+        EigOut o;
+        eig_smallest(s6, o);
+        e0 = static_cast<float>(o.vz);
+        e1 = static_cast<float>(o.vy);
+        e2 = static_cast<float>(o.vx);
+        l1 = o.l1; l2 = o.l2; l3 = o.l3; fa = o.fa;
+        fl = o.degenerate ? ST_FLAG_DEGENERATE : 0u;
+        if (p.has_axis && fibre_angles(o.vz, o.vy, o.vx, p.center, p.dir, pz, py,
+                                       static_cast<double>(xv), ha, ia))
+          fl |= ST_FLAG_ON_AXIS;
+      }
+      if (p.e3) { p.e3[i] = e0; p.e3[n + i] = e1; p.e3[2 * n + i] = e2; }
+      if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
+      if (p.fa) p.fa[i] = fa;
+      if (p.ha) p.ha[i] = ha;
+      if (p.ia) p.ia[i] = ia;
+      if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
 }
 
 template <int R>
 hipError_t launch_xgrad_r(const XGradParams& p, hipStream_t stream) {
-  const int64_t blocks = p.x_tiles * ((p.nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-  hipLaunchKernelGGL((k_xgrad<R>), dim3(static_cast<unsigned>(blocks)), dim3(64, kRowsPerBlock), 0,
-                     stream, p);
+  const int64_t blocks = p.x_tiles * p.nrows;
+  hipLaunchKernelGGL((k_xgrad<R>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
   return hipGetLastError();
 }
 
 template <int R>
 hipError_t launch_xfinal_r(const XFinalParams& p, hipStream_t stream) {
-  const int64_t blocks = p.x_tiles * ((p.nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-  hipLaunchKernelGGL((k_xfinal<R>), dim3(static_cast<unsigned>(blocks)), dim3(64, kRowsPerBlock), 0,
-                     stream, p);
+  const int64_t blocks = p.x_tiles * p.nrows;
+  hipLaunchKernelGGL((k_xfinal<R>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
   return hipGetLastError();
 }
 

@@ -32,126 +32,164 @@ __device__ __forceinline__ int reflect_lane(int m, int n) {
 __device__ __forceinline__ float load_as_float(const uint16_t* p) { return static_cast<float>(*p); }
 __device__ __forceinline__ float load_as_float(const float* p) { return *p; }
 
-// Helix and intrusion angles of the fibre vector v (any length) at voxel
-// (pz, py, px) in the cylindrical frame about the axis through c with unit
-// direction a (all (z, y, x)): e_r is the unit radial vector, e_t = a x e_r
-// taken in right-handed (x, y, z) order, and with f_* = v . e_*,
-// HA = atan2(f_a sgn f_t, |f_t|), IA = atan2(f_r sgn f_t, |f_t|), sgn(0) = +1.
-// Returns true (and leaves ha = ia = 0) when the voxel lies on the axis.
+// Helix and intrusion angles of the unit fibre vector v at voxel (pz, py, px)
+// in the cylindrical frame about the axis through c with unit direction a
+// (all (z, y, x)).  With q_perp the component of (p - c) normal to the axis
+// (length r), e_r = q_perp / r and e_t = a x e_r (right-handed (x, y, z)
+// order); f_* = v . e_*, HA = atan2(f_a sgn f_t, |f_t|) and
+// IA = atan2(f_r sgn f_t, |f_t|) with sgn(0) = +1.  f_r and f_t are formed
+// from the unnormalised q_perp and a x q_perp (both scaled by r), so only HA
+// needs r itself.  Returns true (ha = ia = 0) when the voxel lies on the axis.
 __device__ __forceinline__ bool fibre_angles(double vz, double vy, double vx, const double c[3],
                                              const double a[3], double pz, double py, double px,
                                              float& ha, float& ia) {
   const double qz = pz - c[0], qy = py - c[1], qx = px - c[2];
   const double qa = qz * a[0] + qy * a[1] + qx * a[2];
   const double ez = qz - qa * a[0], ey = qy - qa * a[1], ex = qx - qa * a[2];
-  const double rr = sqrt(ez * ez + ey * ey + ex * ex);
-  if (rr < 1e-9) {
+  const double r2 = ez * ez + ey * ey + ex * ex;
+  if (r2 < 1e-18) {
     ha = 0.f;
     ia = 0.f;
     return true;
   }
-  const double ir = 1.0 / rr;
-  const double erz = ez * ir, ery = ey * ir, erx = ex * ir;
-  const double etz = a[2] * ery - a[1] * erx;
-  const double ety = a[0] * erx - a[2] * erz;
-  const double etx = a[1] * erz - a[0] * ery;
-  const double f_r = vz * erz + vy * ery + vx * erx;
-  const double f_t = vz * etz + vy * ety + vx * etx;
-  const double f_a = vz * a[0] + vy * a[1] + vx * a[2];
-  const double sg = f_t >= 0.0 ? 1.0 : -1.0;
-  const float den = static_cast<float>(fabs(f_t));
-  ha = atan2f(static_cast<float>(f_a * sg), den);
-  ia = atan2f(static_cast<float>(f_r * sg), den);
+  const float fz = static_cast<float>(ez), fy = static_cast<float>(ey), fx = static_cast<float>(ex);
+  const float az = static_cast<float>(a[0]), ay = static_cast<float>(a[1]), ax = static_cast<float>(a[2]);
+  // a x q_perp taken in right-handed (x, y, z) order, stored (z, y, x)
+  const float tz = ax * fy - ay * fx;
+  const float ty = az * fx - ax * fz;
+  const float tx = ay * fz - az * fy;
+  const float uz = static_cast<float>(vz), uy = static_cast<float>(vy), ux = static_cast<float>(vx);
+  const float f_r = uz * fz + uy * fy + ux * fx;   // r * (v . e_r)
+  const float f_t = uz * tz + uy * ty + ux * tx;   // r * (v . e_t)
+  const float f_a = uz * az + uy * ay + ux * ax;   // v . a
+  const float r = sqrtf(static_cast<float>(r2));
+  const float den = fabsf(f_t);
+  const float sg = f_t >= 0.f ? 1.f : -1.f;
+  ha = atan2f(f_a * r * sg, den);
+  ia = atan2f(f_r * sg, den);
   return false;
 }
 
-struct VoxelOut {
-  float e3[3];
-  float ev[3];
-  float fa, ha, ia;
-  uint32_t flags;
+// Null vector of S - lam I (S symmetric, components zz, zy, zx, yy, yx, xx):
+// the largest of the three cross products of pairs of its rows (Kopp 2008).
+// Returns it unnormalised with its squared length.
+__device__ __forceinline__ void null_vector(double zz, double zy, double zx, double yy, double yx,
+                                            double xx, double lam, double& vz, double& vy,
+                                            double& vx, double& nn) {
+  const double a = zz - lam, b = yy - lam, c = xx - lam;
+  const double c0z = zy * yx - zx * b, c0y = zx * zy - a * yx, c0x = a * b - zy * zy;  // r0 x r1
+  const double c1z = zy * c - zx * yx, c1y = zx * zx - a * c, c1x = a * yx - zy * zx;  // r0 x r2
+  const double c2z = b * c - yx * yx, c2y = yx * zx - zy * c, c2x = zy * yx - b * zx;  // r1 x r2
+  const double n0 = c0z * c0z + c0y * c0y + c0x * c0x;
+  const double n1 = c1z * c1z + c1y * c1y + c1x * c1x;
+  const double n2 = c2z * c2z + c2y * c2y + c2x * c2x;
+  vz = c0z; vy = c0y; vx = c0x; nn = n0;
+  if (n1 > nn) { vz = c1z; vy = c1y; vx = c1x; nn = n1; }
+  if (n2 > nn) { vz = c2z; vy = c2y; vx = c2x; nn = n2; }
+}
+
+// sin and cos of x in [0, pi/3] by their Taylor series through x^11 / x^12
+// (truncation error below 1e-9, under float32 rounding).
+__device__ __forceinline__ void sincos_small(float x, float& s, float& c) {
+  const float x2 = x * x;
+  s = x * (1.f + x2 * (-1.f / 6.f + x2 * (1.f / 120.f + x2 * (-1.f / 5040.f +
+          x2 * (1.f / 362880.f + x2 * (-1.f / 39916800.f))))));
+  c = 1.f + x2 * (-0.5f + x2 * (1.f / 24.f + x2 * (-1.f / 720.f + x2 * (1.f / 40320.f +
+          x2 * (-1.f / 3628800.f + x2 * (1.f / 479001600.f))))));
+}
+
+// Reciprocal and reciprocal square root in float64: the hardware estimate
+// refined by two Newton-Raphson steps (each squares the relative error).
+__device__ __forceinline__ double rcp64(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
+}
+__device__ __forceinline__ double rsq64(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+struct EigOut {
+  double vz, vy, vx;  // unit e3, canonical sign
+  float l1, l2, l3;   // lambda1 >= lambda2 >= lambda3
+  float fa;
+  bool degenerate;    // trace <= 0 or (lambda2 - lambda3) / trace < 1e-3
 };
 
-// Eigen-decomposition of one symmetric 3x3 tensor (float32 components, solved in
-// float64), fractional anisotropy, degeneracy test and -- if an axis is given --
-// helix and intrusion angles in the cylindrical frame at voxel (pz, py, px).
+// Smallest-eigenvalue eigenvector of one symmetric 3x3 tensor (float32
+// components), its eigenvalues, FA and the degeneracy test.
 //
-// Eigenvalues: trigonometric closed form for the characteristic cubic of the
-// deviatoric tensor (O. K. Smith, "Eigenvalues of a symmetric 3x3 matrix",
-// CACM 1961): with m = tr/3, p = sqrt(|S - mI|_F^2 / 6), r = det((S - mI)/p)/2
-// and phi = acos(r)/3, the roots are m + 2p cos(phi + 2 pi k / 3).
-// Eigenvector of lambda3: the largest cross product of two rows of S - lambda3 I
+// The invariants of the deviatoric part D = S - mI (m = tr/3,
+// p^2 = |D|_F^2 / 6, r = det(D / p) / 2) are formed in float64, and the
+// eigen-angle phi = acos(r)/3 of the trigonometric solution of the
+// characteristic cubic (O. K. Smith, "Eigenvalues of a symmetric 3x3 matrix",
+// CACM 1961; lambda_k = m + 2p cos(phi + 2 pi k / 3)) is taken as
+// (2/3) asin(sqrt((1 - |r|)/2)) (or pi/3 minus that for r < 0), which keeps
+// full relative accuracy where acos(r) is ill-conditioned (|r| -> 1).
+// The eigenvector is the largest cross product of two rows of S - lambda3 I
 // (J. Kopp, "Efficient numerical diagonalization of hermitian 3x3 matrices",
-// 2008), normalised and given the canonical sign.
-// FA = sqrt(3/2 * |S - mI|_F^2 / |S|_F^2), identical to the eigenvalue form.
-__device__ __forceinline__ void solve_voxel(const float s6[6], bool has_axis,
-                                            const double c[3], const double a[3],
-                                            double pz, double py, double px, VoxelOut& o) {
-  const double szz = s6[0], szy = s6[1], szx = s6[2], syy = s6[3], syx = s6[4], sxx = s6[5];
-  const double tr = szz + syy + sxx;
+// 2008), recomputed once with lambda3 replaced by its Rayleigh quotient, which
+// removes the float32 error of the trigonometric step.
+// FA = sqrt(3/2 |D|_F^2 / |S|_F^2), the eigenvalue form rewritten in invariants.
+__device__ __forceinline__ void eig_smallest(const float s6[6], EigOut& o) {
+  const double zz = s6[0], zy = s6[1], zx = s6[2], yy = s6[3], yx = s6[4], xx = s6[5];
+  const double tr = zz + yy + xx;
   const double m = tr * (1.0 / 3.0);
-  const double dz = szz - m, dy = syy - m, dx = sxx - m;
-  const double off = szy * szy + szx * szx + syx * syx;
-  const double p2 = dz * dz + dy * dy + dx * dx + 2.0 * off;
-  const double f2 = szz * szz + syy * syy + sxx * sxx + 2.0 * off;
+  o.vz = 1.0; o.vy = 0.0; o.vx = 0.0;
+  o.degenerate = true;
+  o.fa = 0.f;
+  o.l1 = o.l2 = o.l3 = static_cast<float>(m);
+  if (!(tr > 0.0)) return;
+  const double dz = zz - m, dy = yy - m, dx = xx - m;
+  const double off = zy * zy + zx * zx + yx * yx;
+  const double p2 = dz * dz + dy * dy + dx * dx + 2.0 * off;  // |D|_F^2
+  const double f2 = zz * zz + yy * yy + xx * xx + 2.0 * off;  // |S|_F^2
+  o.fa = static_cast<float>(sqrt(1.5 * p2 * rcp64(f2)));
+  if (!(p2 > 1e-28 * tr * tr)) return;  // isotropic to working precision
+  const double det = dz * (dy * dx - yx * yx) - zy * (zy * dx - yx * zx) + zx * (zy * yx - dy * zx);
+  const double ip = rsq64(p2 * (1.0 / 6.0));  // 1/p
+  const double p = p2 * (1.0 / 6.0) * ip;
+  double r = 3.0 * det * ip * rcp64(p2);      // det / (2 p^3)
+  r = fmin(1.0, fmax(-1.0, r));
+  const float h = static_cast<float>(0.5 * (1.0 - fabs(r)));
+  const float a = (2.f / 3.f) * asinf(sqrtf(h));
+  const float phi = r >= 0.0 ? a : 1.0471975511965976f - a;  // pi/3 - a
+  float sf, cf;
+  sincos_small(phi, sf, cf);
+  const double k3 = 1.7320508075688772;  // sqrt(3)
+  const double cs = cf, sn = sf;
+  const double l3 = m - p * (cs + k3 * sn);
+  const double l1 = m + 2.0 * p * cs;
+  const double l2 = tr - l1 - l3;
+  const double gap = 2.0 * k3 * p * sn;
+  o.l1 = static_cast<float>(l1);
+  o.l2 = static_cast<float>(l2);
+  o.l3 = static_cast<float>(l3);
+  o.degenerate = gap < 1e-3 * tr;
 
-  double l1 = m, l2 = m, l3 = m, gap = 0.0;
-  double vz = 1.0, vy = 0.0, vx = 0.0;
-  if (p2 > 1e-30 * f2 && p2 > 0.0) {
-    const double p = sqrt(p2 * (1.0 / 6.0));
-    const double ip = 1.0 / p;
-    const double bzz = dz * ip, byy = dy * ip, bxx = dx * ip;
-    const double bzy = szy * ip, bzx = szx * ip, byx = syx * ip;
-    const double det = bzz * (byy * bxx - byx * byx) - bzy * (bzy * bxx - byx * bzx) +
-                       bzx * (bzy * byx - byy * bzx);
-    const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
-    const double phi = acos(r) * (1.0 / 3.0);
-    double sn, cs;
-    sincos(phi, &sn, &cs);
-    const double k3 = 1.7320508075688772;  // sqrt(3)
-    l1 = m + 2.0 * p * cs;
-    l2 = m - p * (cs - k3 * sn);
-    l3 = m - p * (cs + k3 * sn);
-    gap = 2.0 * k3 * p * sn;
-
-    const double r0z = szz - l3, r0y = szy, r0x = szx;
-    const double r1z = szy, r1y = syy - l3, r1x = syx;
-    const double r2z = szx, r2y = syx, r2x = sxx - l3;
-    const double az0 = r0y * r1x - r0x * r1y, ay0 = r0x * r1z - r0z * r1x, ax0 = r0z * r1y - r0y * r1z;
-    const double az1 = r0y * r2x - r0x * r2y, ay1 = r0x * r2z - r0z * r2x, ax1 = r0z * r2y - r0y * r2z;
-    const double az2 = r1y * r2x - r1x * r2y, ay2 = r1x * r2z - r1z * r2x, ax2 = r1z * r2y - r1y * r2z;
-    const double n0 = az0 * az0 + ay0 * ay0 + ax0 * ax0;
-    const double n1 = az1 * az1 + ay1 * ay1 + ax1 * ax1;
-    const double n2 = az2 * az2 + ay2 * ay2 + ax2 * ax2;
-    double nb = n0, bz = az0, by = ay0, bx = ax0;
-    if (n1 > nb) { nb = n1; bz = az1; by = ay1; bx = ax1; }
-    if (n2 > nb) { nb = n2; bz = az2; by = ay2; bx = ax2; }
-    if (nb > 0.0) {
-      const double inv = 1.0 / sqrt(nb);
-      vz = bz * inv; vy = by * inv; vx = bx * inv;
-    }
-  }
+  double vz, vy, vx, nn;
+  null_vector(zz, zy, zx, yy, yx, xx, l3, vz, vy, vx, nn);
+  if (!(nn > 0.0)) return;
+  // Rayleigh quotient of the first estimate, then the null vector again
+  const double sz = zz * vz + zy * vy + zx * vx;
+  const double sy = zy * vz + yy * vy + yx * vx;
+  const double sx = zx * vz + yx * vy + xx * vx;
+  const double lr = (vz * sz + vy * sy + vx * sx) * rcp64(nn);
+  double wz, wy, wx, mm;
+  null_vector(zz, zy, zx, yy, yx, xx, lr, wz, wy, wx, mm);
+  if (mm > 0.0) { vz = wz; vy = wy; vx = wx; nn = mm; }
+  const double inv = rsq64(nn);
+  vz *= inv; vy *= inv; vx *= inv;
   // canonical sign: largest |component| positive, ties to the lower axis (z, then y)
-  {
-    const double az = fabs(vz), ay = fabs(vy), ax = fabs(vx);
-    const double lead = (az >= ay && az >= ax) ? vz : (ay >= ax ? vy : vx);
-    if (lead < 0.0) { vz = -vz; vy = -vy; vx = -vx; }
-  }
-  uint32_t flags = 0;
-  if (!(tr > 0.0) || gap < 1e-3 * tr) flags |= ST_FLAG_DEGENERATE;
-
-  float ha = 0.f, ia = 0.f;
-  if (has_axis && fibre_angles(vz, vy, vx, c, a, pz, py, px, ha, ia)) flags |= ST_FLAG_ON_AXIS;
-  o.e3[0] = static_cast<float>(vz);
-  o.e3[1] = static_cast<float>(vy);
-  o.e3[2] = static_cast<float>(vx);
-  o.ev[0] = static_cast<float>(l1);
-  o.ev[1] = static_cast<float>(l2);
-  o.ev[2] = static_cast<float>(l3);
-  o.fa = f2 > 0.0 ? static_cast<float>(sqrt(1.5 * p2 / f2)) : 0.f;
-  o.ha = ha;
-  o.ia = ia;
-  o.flags = flags;
+  const double az = fabs(vz), ay = fabs(vy), ax = fabs(vx);
+  const double lead = (az >= ay && az >= ax) ? vz : (ay >= ax ? vy : vx);
+  if (lead < 0.0) { vz = -vz; vy = -vy; vx = -vx; }
+  o.vz = vz; o.vy = vy; o.vx = vx;
 }
 
 }  // namespace st

@@ -105,7 +105,7 @@ struct XFinalParams {
 
 constexpr int kXVec = 4;                 // consecutive x outputs per lane
 constexpr int kXTile = 64 * kXVec;       // x outputs per wave
-constexpr int kRowsPerBlock = 4;         // one row per wave, 4 waves per block
+constexpr int kRowsPerBlock = 4;         // rows per block of the angle kernel (one per wave)
 
 hipError_t launch_xgrad(int R, const XGradParams& p, hipStream_t stream);
 hipError_t launch_xfinal(int R, const XFinalParams& p, hipStream_t stream);
