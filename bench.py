@@ -36,6 +36,7 @@ OUTPUTS = ("e3", "fa", "ha", "ia")
 # Algorithmic HBM bytes per voxel and per launch of each kernel (input read once,
 # output written once; no halo re-reads), for this workload.
 ALG_BYTES_PER_VOXEL = {
+    "grad_fused": 2 + 24,             # u16 in, 6 products out
     "grad_z": 2 + 8,                  # u16 in, G_z V and D_z V out
     "grad_y": (4 + 8 + 4 + 4) / 2,    # two launches: (1 in, 2 out) and (1 in, 1 out)
     "grad_x_outer": 12 + 24,          # 3 planes in, 6 products out
@@ -43,7 +44,7 @@ ALG_BYTES_PER_VOXEL = {
     "integrate_y": 24 + 24,
     "integrate_x_eigen": 24 + 1 + 12 + 12,  # S + mask in; e3, FA, HA, IA out
 }
-KERNEL_SOURCES = ["k_strided_impl.h", "k_xpass_impl.h", "st_device.h", "st_api.hip"]
+KERNEL_SOURCES = ["k_gradf.hip", "k_strided_impl.h", "k_xpass_impl.h", "st_device.h", "st_api.hip"]
 
 
 def kernel_source_hash():

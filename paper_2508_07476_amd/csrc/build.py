@@ -25,7 +25,7 @@ STRIDED_GROUPS = 8
 UNITS = ([("st_api.hip", [], "st_api"), ("k_strided.hip", [], "k_strided"),
           ("k_xpass.hip", [], "k_xpass"), ("k_xgrad.hip", [], "k_xgrad"),
           ("k_xfinala.hip", [], "k_xfinala"), ("k_xfinalb.hip", [], "k_xfinalb"),
-          ("k_angles.hip", [], "k_angles")] +
+          ("k_angles.hip", [], "k_angles"), ("k_gradf.hip", [], "k_gradf")] +
          [("k_strided_inst.hip", [f"-DST_STRIDED_GROUP={g}"], f"k_strided_g{g}")
           for g in range(STRIDED_GROUPS)])
 # most expensive first, so they do not finish last

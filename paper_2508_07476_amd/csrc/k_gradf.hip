@@ -1,0 +1,162 @@
+// Fused gradient pass: Gaussian-derivative gradient at scale sigma and the
+// six-component outer product in one read of the input volume.
+//
+// Filter order per input plane: y (G and D), then x (three combinations), then
+// z through per-column register windows, so that
+//   g_z = Dz (Gx Gy V),  g_y = Gz (Gx Dy V),  g_x = Gz (Dx Gy V).
+// A block of 4 waves owns a 4 (y) x 64 (x) tile of output columns and a chunk
+// of z outputs.  For every input plane (z halo of R on each side, reflected at
+// the faces) the (4 + 2R) x (64 + 2R) input tile is staged in LDS; the next
+// plane's loads are issued before the current plane is filtered.  Each
+// column's z window lives in registers and shifts by one plane per step.
+// Products leave with non-temporal stores.
+#include "st_device.h"
+
+namespace st {
+namespace {
+
+template <int R, typename Tin>
+__global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
+  constexpr int W = 2 * R + 1;
+  constexpr int TX = kGradTX, TY = kGradTY;
+  constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
+  constexpr int NSTAGE = (RX * RY + 255) / 256;  // staged elements per thread
+  constexpr int NYPOS = (TY * RX + 255) / 256;   // y-filter positions per thread
+  __shared__ float raw[RY * RX];
+  __shared__ float yb[2][TY * RX];
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  int64_t b = blockIdx.x;
+  const int64_t xt = b % p.x_tiles;
+  b /= p.x_tiles;
+  const int64_t yt = b % p.y_tiles;
+  const int chunk_id = static_cast<int>(b / p.y_tiles);
+  const int64_t x0 = xt * TX, y0 = yt * TY;
+  const int64_t nz = p.nz, ny = p.ny, nx = p.nx;
+  const int64_t z0 = static_cast<int64_t>(chunk_id) * p.chunk;
+  const int64_t len = (nz - z0) < p.chunk ? (nz - z0) : p.chunk;
+  const int64_t plane = ny * nx;  // < 2^31 (checked by the host)
+  const Tin* vol = static_cast<const Tin*>(p.vol);
+
+  // in-plane offsets of this thread's staging slots (reflected at the faces)
+  int off[NSTAGE];
+#pragma unroll
+  for (int j = 0; j < NSTAGE; ++j) {
+    int s = tid + 256 * j;
+    if (s >= RX * RY) s = RX * RY - 1;  // padding slots repeat the last element
+    const int row = s / RX, col = s - (s / RX) * RX;
+    const int gy = reflect_lane(static_cast<int>(y0) - R + row, static_cast<int>(ny));
+    const int gx = reflect_lane(static_cast<int>(x0) - R + col, static_cast<int>(nx));
+    off[j] = gy * static_cast<int>(nx) + gx;
+  }
+  float pf[NSTAGE];
+  auto fetch = [&](int64_t zi) {  // loads of input plane zi into pf
+    const Tin* src = vol + reflect(zi, nz) * plane;
+#pragma unroll
+    for (int j = 0; j < NSTAGE; ++j) pf[j] = static_cast<float>(__builtin_nontemporal_load(src + off[j]));
+  };
+
+  // Filter the staged plane (already fetched into pf) along y then x; returns the
+  // three partial results of this thread's column, and prefetches plane `next`.
+  auto filter_plane = [&](int64_t next, bool has_next, float& a, float& bq, float& c) {
+#pragma unroll
+    for (int j = 0; j < NSTAGE; ++j) {
+      const int s = tid + 256 * j;
+      if (s < RX * RY) raw[s] = pf[j];
+    }
+    if (has_next) fetch(next);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NYPOS; ++q) {
+      const int s = tid + 256 * q;
+      if (s < TY * RX) {
+        const int row = s / RX, col = s - (s / RX) * RX;
+        float g = 0.f, d = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const float v = raw[(row + k) * RX + col];
+          g = fmaf(p.wg.w[k], v, g);
+          d = fmaf(p.wd.w[k], v, d);
+        }
+        yb[0][s] = g;
+        yb[1][s] = d;
+      }
+    }
+    __syncthreads();
+    float ga = 0.f, gb = 0.f, dc = 0.f;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const float u = yb[0][ty * RX + tx + k];
+      const float w = yb[1][ty * RX + tx + k];
+      ga = fmaf(p.wg.w[k], u, ga);
+      dc = fmaf(p.wd.w[k], u, dc);
+      gb = fmaf(p.wg.w[k], w, gb);
+    }
+    // materialise the three results here: otherwise the compiler sinks these
+    // sums towards their use in the z filter and keeps every LDS value alive
+    asm volatile("" : "+v"(ga), "+v"(gb), "+v"(dc));
+    a = ga;   // Gx Gy V   -> Dz gives g_z
+    bq = gb;  // Gx Dy V   -> Gz gives g_y
+    c = dc;   // Dx Gy V   -> Gz gives g_x
+  };
+
+  const bool active = (x0 + tx < nx) && (y0 + ty < ny);
+  const int64_t out_col = (y0 + ty) * nx + (x0 + tx);
+
+  // z windows: w*[k] holds the column's partial results of input plane
+  // (current output z) - R + k; they shift by one plane per step (a rolled loop
+  // keeps the code and the register count small).
+  float wa[W], wb[W], wc[W];
+  fetch(z0 - R);
+  const int64_t nplanes = len + 2 * R;
+#pragma unroll 1
+  for (int64_t j = 0; j < nplanes; ++j) {  // block-uniform trip count
+    float a, bq, c;
+    filter_plane(z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
+#pragma unroll
+    for (int k = 0; k < W - 1; ++k) {
+      wa[k] = wa[k + 1];
+      wb[k] = wb[k + 1];
+      wc[k] = wc[k + 1];
+    }
+    wa[W - 1] = a;
+    wb[W - 1] = bq;
+    wc[W - 1] = c;
+    if (j >= 2 * R && active) {
+      float gz = 0.f, gy = 0.f, gx = 0.f;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        gz = fmaf(p.wd.w[k], wa[k], gz);
+        gy = fmaf(p.wg.w[k], wb[k], gy);
+        gx = fmaf(p.wg.w[k], wc[k], gx);
+      }
+      const int64_t i = (z0 + j - 2 * R) * plane + out_col;
+      __builtin_nontemporal_store(gz * gz, p.prod[0] + i);
+      __builtin_nontemporal_store(gz * gy, p.prod[1] + i);
+      __builtin_nontemporal_store(gz * gx, p.prod[2] + i);
+      __builtin_nontemporal_store(gy * gy, p.prod[3] + i);
+      __builtin_nontemporal_store(gy * gx, p.prod[4] + i);
+      __builtin_nontemporal_store(gx * gx, p.prod[5] + i);
+    }
+  }
+}
+
+template <typename Tin, int R>
+hipError_t launch_r(const GradFusedParams& p, hipStream_t stream) {
+  const int64_t blocks = p.x_tiles * p.y_tiles * p.nchunks;
+  hipLaunchKernelGGL((k_grad_fused<R, Tin>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4), 0,
+                     stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream) {
+#define ST_CASE(r) case r: return in_dtype == ST_DTYPE_U16 ? launch_r<uint16_t, r>(p, stream) \
+                                                           : launch_r<float, r>(p, stream);
+  switch (R) { ST_CASE(1) ST_CASE(2) ST_CASE(3) ST_CASE(4) ST_CASE(5) ST_CASE(6) ST_CASE(7) ST_CASE(8)
+    default: return hipErrorInvalidValue; }
+#undef ST_CASE
+}
+
+}  // namespace st

@@ -45,7 +45,11 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   const int64_t a0 = static_cast<int64_t>(chunk_id) * p.chunk;
   const int64_t len = (n - a0) < p.chunk ? (n - a0) : p.chunk;
   // relative sample i <-> axis index a0 - R + i (reflected into [0, n))
-  auto sample = [&](int64_t i) { return load_as_float(in + reflect(a0 - R + i, n) * sa + lx); };
+  // streaming (non-temporal) loads and stores: every sample is read once per
+  // chunk and every output once, so neither should displace cached data
+  auto sample = [&](int64_t i) {
+    return static_cast<float>(__builtin_nontemporal_load(in + reflect(a0 - R + i, n) * sa + lx));
+  };
 
   // win: the 2R+1 samples of the current output; pre: the newest sample of each
   // output of the current block of W outputs, loaded one block ahead so that W
@@ -71,8 +75,8 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
           if constexpr (WITH_D) d = fmaf(p.wd.w[k], u, d);
         }
         if (active) {
-          og[(a0 + t) * sa + lane] = g;
-          if constexpr (WITH_D) od[(a0 + t) * sa + lane] = d;
+          __builtin_nontemporal_store(g, og + (a0 + t) * sa + lane);
+          if constexpr (WITH_D) __builtin_nontemporal_store(d, od + (a0 + t) * sa + lane);
         }
       }
     };

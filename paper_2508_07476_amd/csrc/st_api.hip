@@ -292,7 +292,27 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
   hipError_t e = hipSuccess;
   const char* stage = "";
   do {
-    // gradient: z pass (G, D), y pass, x pass + outer product
+    // gradient at sigma and outer product: one fused pass when the radius and the
+    // plane size allow it, else z pass (G, D), y pass, x pass + outer product
+    const bool fused_grad = ps <= st::kGradMaxRadius && ny * nx <= INT32_MAX;
+    if (fused_grad) {
+      st::GradFusedParams p;
+      std::memset(&p, 0, sizeof(p));
+      p.vol = volume;
+      for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
+      p.nz = nz; p.ny = ny; p.nx = nx;
+      p.x_tiles = (nx + st::kGradTX - 1) / st::kGradTX;
+      p.y_tiles = (ny + st::kGradTY - 1) / st::kGradTY;
+      // split z until there are enough blocks to fill the chip, keeping chunks >= 8R
+      int64_t nch = 1;
+      while (p.x_tiles * p.y_tiles * nch < 4096 && nz / (2 * nch) >= 8 * ps) nch *= 2;
+      p.chunk = (nz + nch - 1) / nch;
+      p.nchunks = static_cast<int>((nz + p.chunk - 1) / p.chunk);
+      p.wg = gs; p.wd = ds;
+      stage = "grad_fused";
+      e = timed("grad_fused", stream, [&] { return st::launch_grad_fused(ps, dtype, p, stream); });
+      if (e != hipSuccess) break;
+    } else {
     {
       st::StridedJob j = {volume, B[0], B[1]};
       stage = "grad_z";
@@ -319,6 +339,7 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
       stage = "grad_x_outer";
       e = timed("grad_x_outer", stream, [&] { return st::launch_xgrad(ps, p, stream); });
       if (e != hipSuccess) break;
+    }
     }
     // integration: z pass, y pass (6 components each)
     {

@@ -110,6 +110,25 @@ constexpr int kRowsPerBlock = 4;         // rows per block of the angle kernel (
 hipError_t launch_xgrad(int R, const XGradParams& p, hipStream_t stream);
 hipError_t launch_xfinal(int R, const XFinalParams& p, hipStream_t stream);
 
+// ---- fused gradient: Gaussian-derivative gradient at sigma and outer product ----
+// One pass over the input: every block owns a 4 x 64 (y, x) column tile and a
+// chunk of z; each input plane of the chunk (plus z halo) is staged in LDS,
+// filtered along y and then x, and the three partial results of each column
+// enter register windows that are filtered along z.
+struct GradFusedParams {
+  const void* vol;
+  float* prod[6];     // zz, zy, zx, yy, yx, xx
+  int64_t nz, ny, nx;
+  int64_t x_tiles, y_tiles;
+  int64_t chunk;      // z outputs per block
+  int nchunks;
+  Taps wg;
+  Taps wd;
+};
+constexpr int kGradTX = 64, kGradTY = 4;
+constexpr int kGradMaxRadius = 8;  // larger sigma radii use the three separate passes
+hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream);
+
 // ---- standalone angles ------------------------------------------------------
 struct AnglesParams {
   const float* e3;

@@ -69,6 +69,8 @@ CASES = [
     ((1, 1, 1), "u16", 1.0, 1.0, False, None),
     ((9, 70, 2), "u16", 2.0, 3.0, True, (0.0, 1.0, 0.0)),
     ((130, 12, 9), "f32", 1.2, 6.0, False, (1.0, 0.5, 0.0)),   # long z axis (several chunks), R 24
+    ((26, 44, 90), "u16", 2.6, 3.0, True, (1.0, -0.4, 0.3)),   # sigma radius 10: three-pass gradient
+    ((70, 9, 131), "f32", 2.0, 2.0, False, (0.0, 1.0, 1.0)),   # sigma radius 8: largest fused gradient
 ]
 
 
