@@ -26,7 +26,11 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
   __shared__ float yb[2][TY * RX];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  // Blocks are dealt round-robin to the 8 XCDs (each with its own L2); give each
+  // XCD a contiguous run of tiles so that tiles sharing halo rows meet in one L2.
+  const int64_t nblk = p.x_tiles * p.y_tiles * p.nchunks;
   int64_t b = blockIdx.x;
+  if (nblk % 8 == 0) b = (b % 8) * (nblk / 8) + b / 8;
   const int64_t xt = b % p.x_tiles;
   b /= p.x_tiles;
   const int64_t yt = b % p.y_tiles;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
   auto fetch = [&](int64_t zi) {  // loads of input plane zi into pf
     const Tin* src = vol + reflect(zi, nz) * plane;
 #pragma unroll
-    for (int j = 0; j < NSTAGE; ++j) pf[j] = static_cast<float>(__builtin_nontemporal_load(src + off[j]));
+    for (int j = 0; j < NSTAGE; ++j) pf[j] = static_cast<float>(src[off[j]]);  // halo re-read by neighbours: keep cached
   };
 
   // Filter the staged plane (already fetched into pf) along y then x; returns the

@@ -153,37 +153,55 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
   const double pz = static_cast<double>(row / p.ny);
   const double py = static_cast<double>(row % p.ny);
   const int64_t n = p.n;
+  // Voxel v's six tensor components sit in lds[c][4 lane + v]; once read, the
+  // slot receives voxel v's result q (e3 z, y, x, FA, HA, IA), so the four
+  // results of a lane leave as one 16-byte store per output plane.
 #pragma unroll 1
   for (int v = 0; v < kXVec; ++v) {
-    const int64_t xv = x + v;
-    if (xv < p.nx) {
-      const int64_t i = base + xv;
-      const bool inside = p.mask == nullptr || p.mask[i] != 0;
-      float e0 = 0.f, e1 = 0.f, e2 = 0.f, l1 = 0.f, l2 = 0.f, l3 = 0.f, fa = 0.f, ha = 0.f, ia = 0.f;
-      uint32_t fl = ST_FLAG_OUTSIDE_MASK;
-      if (inside) {
-        float s6[6];
+    const int64_t xv = x + v < p.nx ? x + v : p.nx - 1;
+    const int64_t i = base + xv;
+    const bool inside = p.mask == nullptr || p.mask[i] != 0;
+    float s6[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s6[c] = lds[c][kXVec * lane + v];
-        EigOut o;
-        eig_smallest(s6, o);
-        e0 = static_cast<float>(o.vz);
-        e1 = static_cast<float>(o.vy);
-        e2 = static_cast<float>(o.vx);
-        l1 = o.l1; l2 = o.l2; l3 = o.l3; fa = o.fa;
-        fl = o.degenerate ? ST_FLAG_DEGENERATE : 0u;
-        if (p.has_axis && fibre_angles(o.vz, o.vy, o.vx, p.center, p.dir, pz, py,
-                                       static_cast<double>(xv), ha, ia))
-          fl |= ST_FLAG_ON_AXIS;
-      }
-      if (p.e3) { p.e3[i] = e0; p.e3[n + i] = e1; p.e3[2 * n + i] = e2; }
+    for (int c = 0; c < 6; ++c) s6[c] = lds[c][kXVec * lane + v];
+    float r[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float l1 = 0.f, l2 = 0.f, l3 = 0.f;
+    uint32_t fl = ST_FLAG_OUTSIDE_MASK;
+    if (inside) {
+      EigOut o;
+      eig_smallest(s6, o);
+      r[0] = static_cast<float>(o.vz);
+      r[1] = static_cast<float>(o.vy);
+      r[2] = static_cast<float>(o.vx);
+      r[3] = o.fa;
+      l1 = o.l1; l2 = o.l2; l3 = o.l3;
+      fl = o.degenerate ? ST_FLAG_DEGENERATE : 0u;
+      if (p.has_axis && fibre_angles(o.vz, o.vy, o.vx, p.center, p.dir, pz, py,
+                                     static_cast<double>(x + v), r[4], r[5]))
+        fl |= ST_FLAG_ON_AXIS;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) lds[q][kXVec * lane + v] = r[q];
+    if (x + v < p.nx) {  // optional outputs: scalar stores
       if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
-      if (p.fa) p.fa[i] = fa;
-      if (p.ha) p.ha[i] = ha;
-      if (p.ia) p.ia[i] = ia;
       if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
+  float o4[6][kXVec];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const float4 t = *reinterpret_cast<const float4*>(&lds[q][kXVec * lane]);
+    o4[q][0] = t.x; o4[q][1] = t.y; o4[q][2] = t.z; o4[q][3] = t.w;
+  }
+  const bool vec_ok = p.vec_ok != 0;
+  if (p.e3) {
+    store4(p.e3 + base, x, p.nx, vec_ok, o4[0]);
+    store4(p.e3 + n + base, x, p.nx, vec_ok, o4[1]);
+    store4(p.e3 + 2 * n + base, x, p.nx, vec_ok, o4[2]);
+  }
+  if (p.fa) store4(p.fa + base, x, p.nx, vec_ok, o4[3]);
+  if (p.ha) store4(p.ha + base, x, p.nx, vec_ok, o4[4]);
+  if (p.ia) store4(p.ia + base, x, p.nx, vec_ok, o4[5]);
 }
 
 template <int R>
