@@ -13,7 +13,9 @@
 namespace st {
 namespace xpass_impl {
 
-constexpr int stage_slots(int R) { return (kXTile + 2 * R + 63) / 64; }
+// slots cover the tile, both halos and the 4-element over-read of the last
+// matrix-core operand slice
+constexpr int stage_slots(int R) { return (kXTile + 2 * R + 4 + 63) / 64; }
 // LDS row length: every staging slot (64 per lane step) and the 16-byte reads
 // of the last lane's window fit.
 constexpr int lds_row(int R) {
@@ -120,10 +122,40 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
 #undef ST_PROD
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Padded LDS position (one pad word per 16 values): the matrix-core operand
+// reads below are 16 values apart across lanes, and the pad spreads them over
+// distinct banks.
+__device__ __forceinline__ int padpos(int i) { return i + (i >> 4); }
+constexpr int lds_row_pad(int R) { return 68 * stage_slots(R); }
+
+template <int R>
+__device__ __forceinline__ void stage_row_pad(float* lds, const float* row, const int idx[stage_slots(R)],
+                                              int lane) {
+  float v[stage_slots(R)];
+#pragma unroll
+  for (int j = 0; j < stage_slots(R); ++j) v[j] = row[idx[j]];
+#pragma unroll
+  for (int j = 0; j < stage_slots(R); ++j) lds[padpos(lane + 64 * j)] = v[j];
+}
+
+// x integration of the six tensor components on the matrix cores, then the
+// per-voxel eigen-decomposition, FA and angles.
+//
+// For a 256-output row segment, output x = 16 j + i (j: block, i: position in
+// block) is out[16 j + i] = sum_m T[i][m] in[16 j + m] with the banded
+// Toeplitz T[i][m] = w[m - i] (0 <= m - i <= 2R, else 0), m in [0, 16 + 2R).
+// That is a (16 x K) by (K x 16) product, K = 16 + 2R, done as K/4 steps of
+// v_mfma_f32_16x16x4f32: lane l supplies T[l%16][4s + l/16] (constant per
+// wave) and in[16 (l%16) + 4s + l/16] (from LDS), and receives the four
+// consecutive outputs x = 16 (l%16) + 4 (l/16) + r, r = 0..3.
 template <int R>
 __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
-  constexpr int LR = lds_row(R);
-  __shared__ __attribute__((aligned(16))) float lds[6][LR];
+  constexpr int LRP = lds_row_pad(R);
+  constexpr int KS = (16 + 2 * R + 3) / 4;  // K slices of 4
+  __shared__ __attribute__((aligned(16))) float lds[6][LRP];
+  __shared__ float taps[4 * KS + 16];        // taps[k + 15] = w[k], zero outside [0, 2R]
   const int lane = threadIdx.x;
   const int64_t xt = blockIdx.x % p.x_tiles;
   const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
@@ -134,20 +166,46 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
     int idx[stage_slots(R)];
     stage_index<R>(idx, x0, p.nx, lane);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stage_row<R>(lds[c], p.s[c] + base, idx, lane);
+    for (int c = 0; c < 6; ++c) stage_row_pad<R>(lds[c], p.s[c] + base, idx, lane);
+  }
+  for (int t = lane; t < 4 * KS + 16; t += 64) {
+    const int k = t - 15;
+    taps[t] = (k >= 0 && k <= 2 * R) ? p.w.w[k] : 0.f;
   }
   __syncthreads();
 
-  // x-correlation, one component at a time (a rolled loop bounds the live
-  // window); each lane parks its 4 results in its own slots of the component's
-  // staged row, which no lane reads any more (the wave runs in lockstep).
-#pragma unroll 1
-  for (int c = 0; c < 6; ++c) {
-    float o4[kXVec];
-    conv4<R>(lds[c], lane, p.w, o4);
-    *reinterpret_cast<float4*>(&lds[c][kXVec * lane]) = make_float4(o4[0], o4[1], o4[2], o4[3]);
+  const int cb = lane & 15, kq = lane >> 4;  // operand column (block j) and K row
+  // the lane's four voxels are x0 + 16 cb + 4 kq + r; fetch their mask bytes now so
+  // the loads overlap the matrix phase
+  const int64_t x = x0 + 16 * cb + 4 * kq;
+  uint32_t inside_bits = 0xFu;
+  if (p.mask != nullptr) {
+    inside_bits = 0u;
+#pragma unroll
+    for (int r = 0; r < kXVec; ++r) {
+      const int64_t xr = x + r < p.nx ? x + r : p.nx - 1;
+      inside_bits |= (p.mask[base + xr] != 0 ? 1u : 0u) << r;
+    }
   }
-  const int64_t x = x0 + kXVec * lane;
+  float a[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) a[s] = taps[4 * s + kq - cb + 15];
+  // Six independent accumulation chains (one per component), interleaved per K
+  // slice so that consecutive matrix instructions never wait on each other.
+  // The lane's outputs x0 + 16 cb + 4 kq + r, r = 0..3, are parked in
+  // lds[c][4 lane + r] once every operand of the row has been read.
+  v4f acc[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], lds[c][padpos(16 * cb + 4 * s + kq)], acc[c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    *reinterpret_cast<float4*>(&lds[c][kXVec * lane]) = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
   if (x >= p.nx) return;
 
   const double pz = static_cast<double>(row / p.ny);
@@ -160,7 +218,7 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
   for (int v = 0; v < kXVec; ++v) {
     const int64_t xv = x + v < p.nx ? x + v : p.nx - 1;
     const int64_t i = base + xv;
-    const bool inside = p.mask == nullptr || p.mask[i] != 0;
+    const bool inside = (inside_bits >> v) & 1u;
     float s6[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) s6[c] = lds[c][kXVec * lane + v];
