@@ -176,12 +176,12 @@ def main():
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gvoxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "512^3 uint16 helical rod-lattice phantom + annulus mask, sigma=1.5, "
                                "rho=4, truncate=4; outputs e3, FA, HA, IA (plain path)",
                    "shape": list(SHAPE), "sigma": SIGMA, "rho": RHO, "input": "uint16",
-                   "accumulate": "f32", "eigensolve": "f64"},
+                   "arithmetic": "f64", "intermediate_storage": "f32"},
         "roofline": roof,
         "kernels": per_kernel,
     }

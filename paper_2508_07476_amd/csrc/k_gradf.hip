@@ -1,5 +1,6 @@
 // Fused gradient pass: Gaussian-derivative gradient at scale sigma and the
-// six-component outer product in one read of the input volume.
+// six-component outer product in one read of the input volume (filter
+// arithmetic and products in float64, products stored as float32).
 //
 // Filter order per input plane: y (G and D), then x (three combinations), then
 // z through per-column register windows, so that
@@ -22,8 +23,8 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
   constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
   constexpr int NSTAGE = (RX * RY + 255) / 256;  // staged elements per thread
   constexpr int NYPOS = (TY * RX + 255) / 256;   // y-filter positions per thread
-  __shared__ float raw[RY * RX];
-  __shared__ float yb[2][TY * RX];
+  __shared__ float raw[RY * RX];      // input plane (exact in float32)
+  __shared__ double yb[2][TY * RX];   // y-filtered plane, float64
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
   // Blocks are dealt round-robin to the 8 XCDs (each with its own L2); give each
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
 
   // Filter the staged plane (already fetched into pf) along y then x; returns the
   // three partial results of this thread's column, and prefetches plane `next`.
-  auto filter_plane = [&](int64_t next, bool has_next, float& a, float& bq, float& c) {
+  auto filter_plane = [&](int64_t next, bool has_next, double& a, double& bq, double& c) {
 #pragma unroll
     for (int j = 0; j < NSTAGE; ++j) {
       const int s = tid + 256 * j;
@@ -75,26 +76,26 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
       const int s = tid + 256 * q;
       if (s < TY * RX) {
         const int row = s / RX, col = s - (s / RX) * RX;
-        float g = 0.f, d = 0.f;
+        double g = 0.0, d = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const float v = raw[(row + k) * RX + col];
-          g = fmaf(p.wg.w[k], v, g);
-          d = fmaf(p.wd.w[k], v, d);
+          const double v = raw[(row + k) * RX + col];
+          g = fma(p.wg.w[k], v, g);
+          d = fma(p.wd.w[k], v, d);
         }
         yb[0][s] = g;
         yb[1][s] = d;
       }
     }
     __syncthreads();
-    float ga = 0.f, gb = 0.f, dc = 0.f;
+    double ga = 0.0, gb = 0.0, dc = 0.0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-      const float u = yb[0][ty * RX + tx + k];
-      const float w = yb[1][ty * RX + tx + k];
-      ga = fmaf(p.wg.w[k], u, ga);
-      dc = fmaf(p.wd.w[k], u, dc);
-      gb = fmaf(p.wg.w[k], w, gb);
+      const double u = yb[0][ty * RX + tx + k];
+      const double w = yb[1][ty * RX + tx + k];
+      ga = fma(p.wg.w[k], u, ga);
+      dc = fma(p.wd.w[k], u, dc);
+      gb = fma(p.wg.w[k], w, gb);
     }
     // materialise the three results here: otherwise the compiler sinks these
     // sums towards their use in the z filter and keeps every LDS value alive
@@ -110,12 +111,12 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
   // z windows: w*[k] holds the column's partial results of input plane
   // (current output z) - R + k; they shift by one plane per step (a rolled loop
   // keeps the code and the register count small).
-  float wa[W], wb[W], wc[W];
+  double wa[W], wb[W], wc[W];
   fetch(z0 - R);
   const int64_t nplanes = len + 2 * R;
 #pragma unroll 1
   for (int64_t j = 0; j < nplanes; ++j) {  // block-uniform trip count
-    float a, bq, c;
+    double a, bq, c;
     filter_plane(z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
 #pragma unroll
     for (int k = 0; k < W - 1; ++k) {
@@ -127,20 +128,20 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
     wb[W - 1] = bq;
     wc[W - 1] = c;
     if (j >= 2 * R && active) {
-      float gz = 0.f, gy = 0.f, gx = 0.f;
+      double gz = 0.0, gy = 0.0, gx = 0.0;
 #pragma unroll
       for (int k = 0; k < W; ++k) {
-        gz = fmaf(p.wd.w[k], wa[k], gz);
-        gy = fmaf(p.wg.w[k], wb[k], gy);
-        gx = fmaf(p.wg.w[k], wc[k], gx);
+        gz = fma(p.wd.w[k], wa[k], gz);
+        gy = fma(p.wg.w[k], wb[k], gy);
+        gx = fma(p.wg.w[k], wc[k], gx);
       }
       const int64_t i = (z0 + j - 2 * R) * plane + out_col;
-      __builtin_nontemporal_store(gz * gz, p.prod[0] + i);
-      __builtin_nontemporal_store(gz * gy, p.prod[1] + i);
-      __builtin_nontemporal_store(gz * gx, p.prod[2] + i);
-      __builtin_nontemporal_store(gy * gy, p.prod[3] + i);
-      __builtin_nontemporal_store(gy * gx, p.prod[4] + i);
-      __builtin_nontemporal_store(gx * gx, p.prod[5] + i);
+      __builtin_nontemporal_store(static_cast<float>(gz * gz), p.prod[0] + i);
+      __builtin_nontemporal_store(static_cast<float>(gz * gy), p.prod[1] + i);
+      __builtin_nontemporal_store(static_cast<float>(gz * gx), p.prod[2] + i);
+      __builtin_nontemporal_store(static_cast<float>(gy * gy), p.prod[3] + i);
+      __builtin_nontemporal_store(static_cast<float>(gy * gx), p.prod[4] + i);
+      __builtin_nontemporal_store(static_cast<float>(gx * gx), p.prod[5] + i);
     }
   }
 }

@@ -50,11 +50,13 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   auto sample = [&](int64_t i) {
     return static_cast<float>(__builtin_nontemporal_load(in + reflect(a0 - R + i, n) * sa + lx));
   };
+  // window and accumulators in float64 (each sample is widened once, on entry)
 
   // win: the 2R+1 samples of the current output; pre: the newest sample of each
   // output of the current block of W outputs, loaded one block ahead so that W
   // loads per lane are always in flight.
-  float win[W], pre[W];
+  double win[W];
+  float pre[W];
 #pragma unroll
   for (int j = 0; j < 2 * R; ++j) win[j] = sample(j);
 #pragma unroll
@@ -63,20 +65,20 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   for (int64_t tb = 0; tb < len; tb += W) {
     auto step = [&]<int J>(std::integral_constant<int, J>) {
       const int64_t t = tb + J;
-      const float v = pre[J];
+      const double v = pre[J];
       if (t + W < len) pre[J] = sample(t + W + 2 * R);  // same step of the next block
       win[(J + 2 * R) % W] = v;
       if (t < len) {
-        float g = 0.f, d = 0.f;
+        double g = 0.0, d = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const float u = win[(J + k) % W];
-          g = fmaf(p.wg.w[k], u, g);
-          if constexpr (WITH_D) d = fmaf(p.wd.w[k], u, d);
+          const double u = win[(J + k) % W];
+          g = fma(p.wg.w[k], u, g);
+          if constexpr (WITH_D) d = fma(p.wd.w[k], u, d);
         }
         if (active) {
-          __builtin_nontemporal_store(g, og + (a0 + t) * sa + lane);
-          if constexpr (WITH_D) __builtin_nontemporal_store(d, od + (a0 + t) * sa + lane);
+          __builtin_nontemporal_store(static_cast<float>(g), og + (a0 + t) * sa + lane);
+          if constexpr (WITH_D) __builtin_nontemporal_store(static_cast<float>(d), od + (a0 + t) * sa + lane);
         }
       }
     };

@@ -52,7 +52,7 @@ __device__ __forceinline__ void stage_row(float* lds, const float* row, const in
 
 // out[v] = sum_k w[k] * lds[4 lane + v + k], v = 0..3
 template <int R>
-__device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w, float out[kXVec]) {
+__device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w, double out[kXVec]) {
   constexpr int NV = (2 * R + kXVec + 3) / 4;
   float buf[4 * NV];
   const float4* src = reinterpret_cast<const float4*>(lds + 4 * lane);
@@ -66,9 +66,9 @@ __device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w,
   }
 #pragma unroll
   for (int v = 0; v < kXVec; ++v) {
-    float acc = 0.f;
+    double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < 2 * R + 1; ++k) acc = fmaf(w.w[k], buf[v + k], acc);
+    for (int k = 0; k < 2 * R + 1; ++k) acc = fma(w.w[k], static_cast<double>(buf[v + k]), acc);
     out[v] = acc;
   }
 }
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
   stage_row<R>(lds[2], p.gd + base, idx, lane);
   __syncthreads();
 
-  float gx[kXVec], gy[kXVec], gz[kXVec];
+  double gx[kXVec], gy[kXVec], gz[kXVec];
   conv4<R>(lds[0], lane, p.wd, gx);
   conv4<R>(lds[1], lane, p.wg, gy);
   conv4<R>(lds[2], lane, p.wg, gz);
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
   const bool vec_ok = p.vec_ok != 0;
   float t[kXVec];
 #define ST_PROD(idx, A, B)                                        \
-  for (int v = 0; v < kXVec; ++v) t[v] = A[v] * B[v];             \
+  for (int v = 0; v < kXVec; ++v) t[v] = static_cast<float>(A[v] * B[v]); \
   store4(p.prod[idx] + base, x, p.nx, vec_ok, t);
   ST_PROD(0, gz, gz)
   ST_PROD(1, gz, gy)
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
 #undef ST_PROD
 }
 
-typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Padded LDS position (one pad word per 16 values): the matrix-core operand
 // reads below are 16 values apart across lanes, and the pad spreads them over
@@ -140,27 +140,32 @@ __device__ __forceinline__ void stage_row_pad(float* lds, const float* row, cons
   for (int j = 0; j < stage_slots(R); ++j) lds[padpos(lane + 64 * j)] = v[j];
 }
 
-// x integration of the six tensor components on the matrix cores, then the
-// per-voxel eigen-decomposition, FA and angles.
+// x integration of the six tensor components on the float64 matrix cores,
+// then the per-voxel eigen-decomposition, FA and angles.
 //
 // For a 256-output row segment, output x = 16 j + i (j: block, i: position in
 // block) is out[16 j + i] = sum_m T[i][m] in[16 j + m] with the banded
 // Toeplitz T[i][m] = w[m - i] (0 <= m - i <= 2R, else 0), m in [0, 16 + 2R).
 // That is a (16 x K) by (K x 16) product, K = 16 + 2R, done as K/4 steps of
-// v_mfma_f32_16x16x4f32: lane l supplies T[l%16][4s + l/16] (constant per
-// wave) and in[16 (l%16) + 4s + l/16] (from LDS), and receives the four
-// consecutive outputs x = 16 (l%16) + 4 (l/16) + r, r = 0..3.
+// v_mfma_f64_16x16x4f64: lane l supplies T[l%16][4s + l/16] (constant per
+// wave) and in[16 (l%16) + 4s + l/16] (from LDS, widened), and receives the
+// outputs i = l/16 + 4r, r = 0..3, of block j = l%16.  The band is accumulated
+// in ascending tap order, as a sequential float64 FMA chain would.  Each lane
+// then solves exactly those four voxels, taking the tensor from its own
+// accumulators, and the results are transposed through LDS into 16-byte stores.
 template <int R>
 __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
   constexpr int LRP = lds_row_pad(R);
   constexpr int KS = (16 + 2 * R + 3) / 4;  // K slices of 4
   __shared__ __attribute__((aligned(16))) float lds[6][LRP];
-  __shared__ float taps[4 * KS + 16];        // taps[k + 15] = w[k], zero outside [0, 2R]
+  __shared__ double taps[4 * KS + 16];       // taps[k + 15] = w[k], zero outside [0, 2R]
   const int lane = threadIdx.x;
   const int64_t xt = blockIdx.x % p.x_tiles;
   const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
   const int64_t x0 = xt * kXTile;
   const int64_t base = row * p.nx;
+  const int cb = lane & 15, kq = lane >> 4;    // operand column (block j) and K row
+  const int xl = 16 * cb + kq;                 // lane's voxels: x0 + xl + 4 r, r = 0..3
 
   {
     int idx[stage_slots(R)];
@@ -170,81 +175,74 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
   }
   for (int t = lane; t < 4 * KS + 16; t += 64) {
     const int k = t - 15;
-    taps[t] = (k >= 0 && k <= 2 * R) ? p.w.w[k] : 0.f;
+    taps[t] = (k >= 0 && k <= 2 * R) ? p.w.w[k] : 0.0;
   }
-  __syncthreads();
-
-  const int cb = lane & 15, kq = lane >> 4;  // operand column (block j) and K row
-  // the lane's four voxels are x0 + 16 cb + 4 kq + r; fetch their mask bytes now so
-  // the loads overlap the matrix phase
-  const int64_t x = x0 + 16 * cb + 4 * kq;
+  // mask bytes of the lane's voxels, fetched now so the loads overlap the matrix phase
   uint32_t inside_bits = 0xFu;
   if (p.mask != nullptr) {
     inside_bits = 0u;
 #pragma unroll
-    for (int r = 0; r < kXVec; ++r) {
-      const int64_t xr = x + r < p.nx ? x + r : p.nx - 1;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t xr = x0 + xl + 4 * r < p.nx ? x0 + xl + 4 * r : p.nx - 1;
       inside_bits |= (p.mask[base + xr] != 0 ? 1u : 0u) << r;
     }
   }
-  float a[KS];
+  __syncthreads();
+
+  double a[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) a[s] = taps[4 * s + kq - cb + 15];
-  // Six independent accumulation chains (one per component), interleaved per K
-  // slice so that consecutive matrix instructions never wait on each other.
-  // The lane's outputs x0 + 16 cb + 4 kq + r, r = 0..3, are parked in
-  // lds[c][4 lane + r] once every operand of the row has been read.
-  v4f acc[6];
+  // six independent accumulation chains, interleaved per K slice
+  v4d acc[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < 6; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], lds[c][padpos(16 * cb + 4 * s + kq)], acc[c], 0, 0, 0);
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+          a[s], static_cast<double>(lds[c][padpos(16 * cb + 4 * s + kq)]), acc[c], 0, 0, 0);
   }
-#pragma unroll
-  for (int c = 0; c < 6; ++c)
-    *reinterpret_cast<float4*>(&lds[c][kXVec * lane]) = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
-  if (x >= p.nx) return;
+  __syncthreads();  // every operand read before the rows receive results
 
   const double pz = static_cast<double>(row / p.ny);
   const double py = static_cast<double>(row % p.ny);
   const int64_t n = p.n;
-  // Voxel v's six tensor components sit in lds[c][4 lane + v]; once read, the
-  // slot receives voxel v's result q (e3 z, y, x, FA, HA, IA), so the four
-  // results of a lane leave as one 16-byte store per output plane.
 #pragma unroll 1
-  for (int v = 0; v < kXVec; ++v) {
-    const int64_t xv = x + v < p.nx ? x + v : p.nx - 1;
-    const int64_t i = base + xv;
-    const bool inside = (inside_bits >> v) & 1u;
-    float s6[6];
+  for (int r = 0; r < 4; ++r) {
+    const int64_t xv = x0 + xl + 4 * r;
+    const int64_t i = base + (xv < p.nx ? xv : p.nx - 1);
+    const bool inside = (inside_bits >> r) & 1u;
+    double s6[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s6[c] = lds[c][kXVec * lane + v];
-    float r[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < 6; ++c)  // register select (r is a loop variable)
+      s6[c] = r == 0 ? acc[c][0] : r == 1 ? acc[c][1] : r == 2 ? acc[c][2] : acc[c][3];
+    float res[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float l1 = 0.f, l2 = 0.f, l3 = 0.f;
     uint32_t fl = ST_FLAG_OUTSIDE_MASK;
     if (inside) {
       EigOut o;
       eig_smallest(s6, o);
-      r[0] = static_cast<float>(o.vz);
-      r[1] = static_cast<float>(o.vy);
-      r[2] = static_cast<float>(o.vx);
-      r[3] = o.fa;
+      res[0] = static_cast<float>(o.vz);
+      res[1] = static_cast<float>(o.vy);
+      res[2] = static_cast<float>(o.vx);
+      res[3] = o.fa;
       l1 = o.l1; l2 = o.l2; l3 = o.l3;
       fl = o.degenerate ? ST_FLAG_DEGENERATE : 0u;
       if (p.has_axis && fibre_angles(o.vz, o.vy, o.vx, p.center, p.dir, pz, py,
-                                     static_cast<double>(x + v), r[4], r[5]))
+                                     static_cast<double>(xv), res[4], res[5]))
         fl |= ST_FLAG_ON_AXIS;
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) lds[q][kXVec * lane + v] = r[q];
-    if (x + v < p.nx) {  // optional outputs: scalar stores
+    for (int q = 0; q < 6; ++q) lds[q][xl + 4 * r] = res[q];
+    if (xv < p.nx) {  // optional outputs: scalar stores
       if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
       if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
+  __syncthreads();  // every lane's results in place before the transposed reads
+  const int64_t x = x0 + kXVec * lane;
+  if (x >= p.nx) return;
   float o4[6][kXVec];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {

@@ -41,8 +41,8 @@ int radius_of(double scale, double truncate) {
 }
 
 // Normalised sampled Gaussian (w0) and derivative (w1 = k/s^2 w0) taps of
-// radius R, computed in double and rounded to float, stored centred in a
-// window of radius Rpad >= R (the outer taps are exact zeros).
+// radius R in double, stored centred in a window of radius Rpad >= R (the
+// outer taps are exact zeros).
 void make_taps(double s, int R, int Rpad, st::Taps& w0, st::Taps* w1) {
   double g[st::kMaxTaps];
   double sum = 0.0;
@@ -54,8 +54,8 @@ void make_taps(double s, int R, int Rpad, st::Taps& w0, st::Taps* w1) {
   if (w1) std::memset(w1, 0, sizeof(*w1));
   for (int k = -R; k <= R; ++k) {
     const double v = g[k + R] / sum;
-    w0.w[k + Rpad] = static_cast<float>(v);
-    if (w1) w1->w[k + Rpad] = static_cast<float>((double(k) / (s * s)) * v);
+    w0.w[k + Rpad] = v;
+    if (w1) w1->w[k + Rpad] = (double(k) / (s * s)) * v;
   }
 }
 

@@ -121,7 +121,7 @@ struct EigOut {
   bool degenerate;    // trace <= 0 or (lambda2 - lambda3) / trace < 1e-3
 };
 
-// Smallest-eigenvalue eigenvector of one symmetric 3x3 tensor (float32
+// Smallest-eigenvalue eigenvector of one symmetric 3x3 tensor (float64
 // components), its eigenvalues, FA and the degeneracy test.
 //
 // The invariants of the deviatoric part D = S - mI (m = tr/3,
@@ -136,7 +136,7 @@ struct EigOut {
 // 2008), recomputed once with lambda3 replaced by its Rayleigh quotient, which
 // removes the float32 error of the trigonometric step.
 // FA = sqrt(3/2 |D|_F^2 / |S|_F^2), the eigenvalue form rewritten in invariants.
-__device__ __forceinline__ void eig_smallest(const float s6[6], EigOut& o) {
+__device__ __forceinline__ void eig_smallest(const double s6[6], EigOut& o) {
   const double zz = s6[0], zy = s6[1], zx = s6[2], yy = s6[3], yx = s6[4], xx = s6[5];
   const double tr = zz + yy + xx;
   const double m = tr * (1.0 / 3.0);

@@ -33,10 +33,12 @@ inline int padded_radius(int R, bool sigma) {
   return -1;
 }
 
-// Filter taps in float32, index m <-> offset k = m - R.  Passed by value as a
-// kernel argument so every tap lives in a scalar register.
+// Filter taps in float64, index m <-> offset k = m - R.  Passed by value as a
+// kernel argument so every tap lives in scalar registers.  All filter
+// arithmetic runs in float64 (an FMA of either width issues at the same rate);
+// intermediate planes are stored in float32.
 struct Taps {
-  float w[kMaxTaps];
+  double w[kMaxTaps];
 };
 
 // ---- strided-axis correlation (z or y) -------------------------------------
