@@ -13,8 +13,7 @@
 namespace st {
 namespace xpass_impl {
 
-// slots cover the tile, both halos and the 4-element over-read of the last
-// matrix-core operand slice
+// slots cover the tile and both halos, rounded up to whole 16-byte windows
 constexpr int stage_slots(int R) { return (kXTile + 2 * R + 4 + 63) / 64; }
 // LDS row length: every staging slot (64 per lane step) and the 16-byte reads
 // of the last lane's window fit.
@@ -50,26 +49,30 @@ __device__ __forceinline__ void stage_row(float* lds, const float* row, const in
   for (int j = 0; j < stage_slots(R); ++j) lds[lane + 64 * j] = v[j];
 }
 
-// out[v] = sum_k w[k] * lds[4 lane + v + k], v = 0..3
+// out[v] = sum_k w[k] * lds[4 lane + v + k], v = 0..3, in float64.  The
+// window is streamed through in 16-byte pieces: each value is widened once and
+// enters the (up to) four sums it belongs to, each sum taking its taps in
+// ascending order.
 template <int R>
 __device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w, double out[kXVec]) {
   constexpr int NV = (2 * R + kXVec + 3) / 4;
-  float buf[4 * NV];
   const float4* src = reinterpret_cast<const float4*>(lds + 4 * lane);
+#pragma unroll
+  for (int v = 0; v < kXVec; ++v) out[v] = 0.0;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     const float4 t = src[q];
-    buf[4 * q + 0] = t.x;
-    buf[4 * q + 1] = t.y;
-    buf[4 * q + 2] = t.z;
-    buf[4 * q + 3] = t.w;
-  }
+    const float e[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-  for (int v = 0; v < kXVec; ++v) {
-    double acc = 0.0;
+    for (int u = 0; u < 4; ++u) {
+      const int j = 4 * q + u;
+      const double d = static_cast<double>(e[u]);
 #pragma unroll
-    for (int k = 0; k < 2 * R + 1; ++k) acc = fma(w.w[k], static_cast<double>(buf[v + k]), acc);
-    out[v] = acc;
+      for (int v = 0; v < kXVec; ++v) {
+        const int k = j - v;
+        if (k >= 0 && k <= 2 * R) out[v] = fma(w.w[k], d, out[v]);
+      }
+    }
   }
 }
 
@@ -122,101 +125,57 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
 #undef ST_PROD
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// Padded LDS position (one pad word per 16 values): the matrix-core operand
-// reads below are 16 values apart across lanes, and the pad spreads them over
-// distinct banks.
-__device__ __forceinline__ int padpos(int i) { return i + (i >> 4); }
-constexpr int lds_row_pad(int R) { return 68 * stage_slots(R); }
-
-template <int R>
-__device__ __forceinline__ void stage_row_pad(float* lds, const float* row, const int idx[stage_slots(R)],
-                                              int lane) {
-  float v[stage_slots(R)];
-#pragma unroll
-  for (int j = 0; j < stage_slots(R); ++j) v[j] = row[idx[j]];
-#pragma unroll
-  for (int j = 0; j < stage_slots(R); ++j) lds[padpos(lane + 64 * j)] = v[j];
-}
-
-// x integration of the six tensor components on the float64 matrix cores,
-// then the per-voxel eigen-decomposition, FA and angles.
-//
-// For a 256-output row segment, output x = 16 j + i (j: block, i: position in
-// block) is out[16 j + i] = sum_m T[i][m] in[16 j + m] with the banded
-// Toeplitz T[i][m] = w[m - i] (0 <= m - i <= 2R, else 0), m in [0, 16 + 2R).
-// That is a (16 x K) by (K x 16) product, K = 16 + 2R, done as K/4 steps of
-// v_mfma_f64_16x16x4f64: lane l supplies T[l%16][4s + l/16] (constant per
-// wave) and in[16 (l%16) + 4s + l/16] (from LDS, widened), and receives the
-// outputs i = l/16 + 4r, r = 0..3, of block j = l%16.  The band is accumulated
-// in ascending tap order, as a sequential float64 FMA chain would.  Each lane
-// then solves exactly those four voxels, taking the tensor from its own
-// accumulators, and the results are transposed through LDS into 16-byte stores.
+// x integration of the six tensor components (float64, on the vector ALUs:
+// the float64 matrix-core and vector paths share issue slots, and the banded
+// form costs fewer operations on the vector path), then the per-voxel
+// eigen-decomposition, FA and angles of the lane's kXVec consecutive voxels.
+// Results are parked in the staged rows (free once every window has been read)
+// and leave as 16-byte stores.
 template <int R>
 __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
-  constexpr int LRP = lds_row_pad(R);
-  constexpr int KS = (16 + 2 * R + 3) / 4;  // K slices of 4
-  __shared__ __attribute__((aligned(16))) float lds[6][LRP];
-  __shared__ double taps[4 * KS + 16];       // taps[k + 15] = w[k], zero outside [0, 2R]
+  constexpr int LR = lds_row(R);
+  __shared__ __attribute__((aligned(16))) float lds[6][LR];
   const int lane = threadIdx.x;
   const int64_t xt = blockIdx.x % p.x_tiles;
   const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
   const int64_t x0 = xt * kXTile;
   const int64_t base = row * p.nx;
-  const int cb = lane & 15, kq = lane >> 4;    // operand column (block j) and K row
-  const int xl = 16 * cb + kq;                 // lane's voxels: x0 + xl + 4 r, r = 0..3
+  const int64_t x = x0 + kXVec * lane;
 
   {
     int idx[stage_slots(R)];
     stage_index<R>(idx, x0, p.nx, lane);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stage_row_pad<R>(lds[c], p.s[c] + base, idx, lane);
+    for (int c = 0; c < 6; ++c) stage_row<R>(lds[c], p.s[c] + base, idx, lane);
   }
-  for (int t = lane; t < 4 * KS + 16; t += 64) {
-    const int k = t - 15;
-    taps[t] = (k >= 0 && k <= 2 * R) ? p.w.w[k] : 0.0;
-  }
-  // mask bytes of the lane's voxels, fetched now so the loads overlap the matrix phase
+  // mask bytes of the lane's voxels, fetched now so the loads overlap the filtering
   uint32_t inside_bits = 0xFu;
   if (p.mask != nullptr) {
     inside_bits = 0u;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t xr = x0 + xl + 4 * r < p.nx ? x0 + xl + 4 * r : p.nx - 1;
-      inside_bits |= (p.mask[base + xr] != 0 ? 1u : 0u) << r;
+    for (int v = 0; v < kXVec; ++v) {
+      const int64_t xr = x + v < p.nx ? x + v : p.nx - 1;
+      inside_bits |= (p.mask[base + xr] != 0 ? 1u : 0u) << v;
     }
   }
   __syncthreads();
 
-  double a[KS];
+  double acc[6][kXVec];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) a[s] = taps[4 * s + kq - cb + 15];
-  // six independent accumulation chains, interleaved per K slice
-  v4d acc[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < KS; ++s) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-          a[s], static_cast<double>(lds[c][padpos(16 * cb + 4 * s + kq)]), acc[c], 0, 0, 0);
-  }
-  __syncthreads();  // every operand read before the rows receive results
+  for (int c = 0; c < 6; ++c) conv4<R>(lds[c], lane, p.w, acc[c]);
+  __syncthreads();  // every window read before the rows receive results
 
   const double pz = static_cast<double>(row / p.ny);
   const double py = static_cast<double>(row % p.ny);
   const int64_t n = p.n;
 #pragma unroll 1
-  for (int r = 0; r < 4; ++r) {
-    const int64_t xv = x0 + xl + 4 * r;
-    const int64_t i = base + (xv < p.nx ? xv : p.nx - 1);
-    const bool inside = (inside_bits >> r) & 1u;
+  for (int v = 0; v < kXVec; ++v) {
+    const int64_t xv = x + v;
+    const bool inside = (inside_bits >> v) & 1u;
     double s6[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c)  // register select (r is a loop variable)
-      s6[c] = r == 0 ? acc[c][0] : r == 1 ? acc[c][1] : r == 2 ? acc[c][2] : acc[c][3];
+    for (int c = 0; c < 6; ++c)  // register select (v is a loop variable)
+      s6[c] = v == 0 ? acc[c][0] : v == 1 ? acc[c][1] : v == 2 ? acc[c][2] : acc[c][3];
     float res[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float l1 = 0.f, l2 = 0.f, l3 = 0.f;
     uint32_t fl = ST_FLAG_OUTSIDE_MASK;
@@ -234,15 +193,15 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
         fl |= ST_FLAG_ON_AXIS;
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) lds[q][xl + 4 * r] = res[q];
+    for (int q = 0; q < 6; ++q) lds[q][kXVec * lane + v] = res[q];
     if (xv < p.nx) {  // optional outputs: scalar stores
+      const int64_t i = base + xv;
       if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
       if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
-  __syncthreads();  // every lane's results in place before the transposed reads
-  const int64_t x = x0 + kXVec * lane;
   if (x >= p.nx) return;
+  // the lane reads back only what it wrote: no barrier needed
   float o4[6][kXVec];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
