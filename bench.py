@@ -44,6 +44,24 @@ ALG_BYTES_PER_VOXEL = {
     "integrate_y": 24 + 24,
     "integrate_x_eigen": 24 + 1 + 12 + 12,  # S + mask in; e3, FA, HA, IA out
 }
+# Algorithmic vector-ALU operations per voxel (one FMA or one float32 op = one
+# lane-operation = 2 flop-equivalents): separable filters 2R+1 FMAs per 1-D
+# pass (8 gradient passes at sigma, 6 components per integration axis at rho),
+# 6 products, about 220 for the eigen-decomposition, FA and angles.
+EIGEN_ANGLE_OPS = 220
+
+
+def alg_ops_per_voxel(kernel, rs, rr):
+    return {"grad_fused": 8 * (2 * rs + 1) + 6,
+            "integrate_z": 6 * (2 * rr + 1),
+            "integrate_y": 6 * (2 * rr + 1),
+            "integrate_x_eigen": 6 * (2 * rr + 1) + EIGEN_ANGLE_OPS}.get(kernel)
+
+
+# vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s
+# (float64 FMA and non-packed float32 issue at the same rate), i.e. 78.6 TFLOP/s
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+
 KERNEL_SOURCES = ["k_gradf.hip", "k_strided_impl.h", "k_xpass_impl.h", "st_device.h", "st_api.hip"]
 
 
@@ -159,19 +177,38 @@ def main():
     ms_per_step = total_ms / args.steps
     value = nvox * args.steps / (total_ms / 1e3) / 1e9
 
-    # dominant kernel
-    dom = max(kern.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dlaunch) = dom
-    avg_s = dms / dlaunch / 1e3
-    bytes_per_launch = ALG_BYTES_PER_VOXEL[dname] * nvox
-    achieved = bytes_per_launch / avg_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dname, nvox, dlaunch),
-            "kernel": dname, "avg_launch_ms": round(avg_s * 1e3, 4),
-            "alg_bytes_per_voxel": ALG_BYTES_PER_VOXEL[dname]}
-    per_kernel = {k: {"avg_ms": round(v[0] / v[1], 4), "launches_per_step": v[1] / args.steps,
-                      "alg_GBps": round(ALG_BYTES_PER_VOXEL[k] * nvox / (v[0] / v[1] / 1e3) / 1e9, 1)}
-                  for k, v in kern.items()}
+    # dominant kernel, placed against whichever roof binds it
+    rs, rr = int(TRUNCATE * SIGMA + 0.5), int(TRUNCATE * RHO + 0.5)
+
+    def roof_for(name, ms, launches):
+        avg_s = ms / launches / 1e3
+        gbs = ALG_BYTES_PER_VOXEL[name] * nvox / avg_s / 1e9
+        ops = alg_ops_per_voxel(name, rs, rr)
+        tflops = None if ops is None else ops * 2 * nvox / avg_s / 1e12
+        return avg_s, gbs, ops, tflops
+
+    dname, (dms, dlaunch) = max(kern.items(), key=lambda kv: kv[1][0])
+    avg_s, gbs, ops, tflops = roof_for(dname, dms, dlaunch)
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = None if tflops is None else tflops / VALU_PEAK_TFLOPS
+    common = {"traffic": traffic_for(dname, nvox, dlaunch), "kernel": dname,
+              "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if alu_frac is not None and alu_frac > hbm_frac:
+        roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": round(VALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), **common,
+                "alg_ops_per_voxel": ops, "hbm_achieved_GBps": round(gbs, 1),
+                "hbm_frac": round(hbm_frac, 4), "alg_bytes_per_voxel": ALG_BYTES_PER_VOXEL[dname]}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4), **common,
+                "alg_bytes_per_voxel": ALG_BYTES_PER_VOXEL[dname]}
+    per_kernel = {}
+    for k, v in kern.items():
+        a_s, g, o, t = roof_for(k, v[0], v[1])
+        per_kernel[k] = {"avg_ms": round(a_s * 1e3, 4), "launches_per_step": v[1] / args.steps,
+                         "alg_GBps": round(g, 1), "hbm_frac": round(g / HBM_PEAK_GBS, 4)}
+        if t is not None:
+            per_kernel[k]["alu_frac"] = round(t / VALU_PEAK_TFLOPS, 4)
 
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gvoxels/s", "n_gpus": 1,
