@@ -18,6 +18,7 @@ import oracle
 import paper_2508_07476_amd as st
 from phantom import helix
 
+from _oracle_worker import oracle_block
 from _parity import compare
 
 SIGMA, RHO = 2.0, 6.0
@@ -42,18 +43,51 @@ def run_full(device="cuda:0"):
     return spec, ph, res
 
 
-def compare_block(ph, res, origin, B):
+def crop_for(ph, origin, B):
+    """Host copy of the block at ``origin`` padded by R_sigma + R_rho (clipped at the faces)."""
     halo = oracle.radius(SIGMA) + oracle.radius(RHO)
     lo = [max(0, c - halo) for c in origin]
     hi = [min(SHAPE[i], origin[i] + B + halo) for i in range(3)]
-    crop = ph["volume"][lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].cpu().numpy()
-    o = oracle.compute(crop, None, SIGMA, RHO, axis_center=ph["center"], axis_direction=ph["direction"],
-                       origin=tuple(lo))
-    s = tuple(slice(origin[i] - lo[i], origin[i] - lo[i] + B) for i in range(3))
-    ob = {k: (v[(slice(None),) + s] if v.ndim == 4 else v[s]) for k, v in o.items() if v is not None}
+    return ph["volume"][lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].cpu().numpy(), lo
+
+
+def gpu_block(res, origin, B):
     gs = tuple(slice(origin[i], origin[i] + B) for i in range(3))
-    gb = {k: (v[(slice(None),) + gs] if v.dim() == 4 else v[gs]).cpu().numpy() for k, v in res.items()}
+    return {k: (v[(slice(None),) + gs] if v.dim() == 4 else v[gs]).cpu().numpy() for k, v in res.items()}
+
+
+def compare_block(ph, res, origin, B, ob=None):
+    if ob is None:
+        crop, lo = crop_for(ph, origin, B)
+        ob = oracle_block(crop, lo, origin, B, SIGMA, RHO, ph["center"], ph["direction"])
+    gb = gpu_block(res, origin, B)
     return compare(gb, ob, (B, B, B), ph["center"], ph["direction"], origin=origin), ob
+
+
+def time_full(ph, res, reps=3):
+    """Average time of ``reps`` further whole-volume runs into the same outputs and
+    workspace (inputs resident), with the per-pass split from the library's
+    event profiler."""
+    vol = ph["volume"]
+    torch.cuda.empty_cache()  # the first call's library-sized workspace is no longer needed
+    ws = torch.empty(st.st_workspace_bytes(tuple(vol.shape)), dtype=torch.uint8, device=vol.device)
+    run = lambda: st.st_compute(vol, SIGMA, RHO, axis_center=ph["center"], axis_direction=ph["direction"],
+                                outputs=tuple(res.keys()), out=res, workspace=ws)
+    run()
+    torch.cuda.synchronize()
+    st.profile_reset()
+    st.profile_enable(True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        run()
+    t1.record()
+    torch.cuda.synchronize()
+    st.profile_enable(False)
+    kern = st.profile_read()
+    ms = t0.elapsed_time(t1) / reps
+    del ws
+    return ms, {k: v[0] / v[1] for k, v in kern.items()}
 
 
 def block_origins(count, B, seed=2):
