@@ -174,8 +174,12 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
     const bool inside = (inside_bits >> v) & 1u;
     double s6[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c)  // register select (v is a loop variable)
-      s6[c] = v == 0 ? acc[c][0] : v == 1 ? acc[c][1] : v == 2 ? acc[c][2] : acc[c][3];
+    for (int c = 0; c < 6; ++c) {  // voxel v's tensor is always in slot 0: rotate the rest down
+      s6[c] = acc[c][0];
+      acc[c][0] = acc[c][1];
+      acc[c][1] = acc[c][2];
+      acc[c][2] = acc[c][3];
+    }
     float res[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float l1 = 0.f, l2 = 0.f, l3 = 0.f;
     uint32_t fl = ST_FLAG_OUTSIDE_MASK;
