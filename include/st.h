@@ -29,8 +29,9 @@
  * no formula): for scale s and `truncate` t the kernel radius is
  * R = floor(t*s + 0.5); taps w0(k) = exp(-k^2/(2 s^2)) / sum_j exp(-j^2/(2 s^2))
  * and w1(k) = (k/s^2) w0(k) for k in [-R, R], applied as 1-D correlations with
- * half-sample symmetric reflection at every face.  Accumulation is float32;
- * the eigen-decomposition, FA and the frame run in float64.
+ * half-sample symmetric reflection at every face.  Filter arithmetic runs in
+ * float64 with float32 intermediate planes; the eigen-decomposition, FA and
+ * the frame run in float64 with float32 trigonometric steps.
  */
 #ifndef ST_H_
 #define ST_H_
@@ -144,6 +145,76 @@ int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
                        const double* axis_center, const double* axis_direction,
                        float* e3, float* fa, float* ha, float* ia, float* confidence,
                        void* stream);
+
+/*
+ * Chunk batches (the paper's chunk-based processing with padding, Implementation
+ * section): many independent volumes -- typically halo-padded crops of one
+ * large scan -- run through the st_compute path as one unit of work.
+ *
+ * st_batch_create validates every chunk (as st_compute would), assigns the
+ * chunks to `lanes` concurrent chains (largest first, each to the chain with
+ * the least work so far), gives every chain its own workspace slot and
+ * captures the whole batch once into a HIP graph.  st_batch_launch replays it
+ * on `stream`; replays recompute every output.  st_batch_tune times candidate
+ * launch configurations (chain count, how far each pass splits its filtered
+ * axis, graph replay vs direct multi-stream enqueue) on the real chunks and
+ * keeps the fastest; results do not depend on the configuration (bitwise).
+ * The chunk buffers must stay valid, and must not be written, while a launch
+ * may run; chunks may not share output buffers.
+ */
+typedef struct st_chunk {
+  const void* volume;     /* device [nz][ny][nx] of dtype */
+  int dtype;              /* ST_DTYPE_U16 or ST_DTYPE_F32 */
+  const uint8_t* mask;    /* device [nz][ny][nx] or NULL */
+  int64_t nz, ny, nx;
+  double rho;             /* integration scale of this chunk */
+  double origin[3];       /* (z, y, x) of volume[0][0][0] in the axis' coordinates */
+  float* e3;              /* outputs as in st_compute, device or NULL */
+  float* evals;
+  float* fa;
+  float* ha;
+  float* ia;
+  uint8_t* flags;
+} st_chunk;
+
+typedef struct st_batch st_batch;  /* opaque */
+
+/* Largest chain count of a batch. */
+#define ST_BATCH_MAX_LANES 8
+
+/* Workspace bytes a batch of these chunks needs with `lanes` chains (0 = room
+ * for ST_BATCH_MAX_LANES, as an autotuned batch uses); 0 if a chunk's sizes
+ * are invalid. */
+size_t st_batch_workspace_bytes(const st_chunk* chunks, int nchunks, int lanes);
+
+/* Builds a batch.  chunks: HOST array of nchunks >= 1 descriptors (copied).
+ * sigma, truncate: as in st_compute, shared by every chunk.  axis_center /
+ * axis_direction: HOST (z, y, x) or both NULL (then ha / ia must be NULL).
+ * lanes: 1..ST_BATCH_MAX_LANES, or 0 to start at 4 and let st_batch_tune choose.
+ * workspace: device buffer of st_batch_workspace_bytes(chunks, nchunks, lanes)
+ * bytes, or NULL for the batch to allocate (and free in st_batch_destroy).
+ * On success *out holds the batch (owned by the caller, release with
+ * st_batch_destroy).  Synchronous: returns after the graph is built. */
+int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double truncate,
+                    const double* axis_center, const double* axis_direction, int lanes,
+                    void* workspace, size_t workspace_bytes, st_batch** out);
+
+/* Enqueues the whole batch on `stream`. */
+int st_batch_launch(st_batch* batch, void* stream);
+
+/* Autotuning: runs the batch for every candidate configuration (each once to
+ * warm up, then `reps` >= 1 timed runs on `stream`), keeps the fastest and
+ * rebuilds the graph for it.  Synchronises `stream`.  Candidates are limited
+ * to the chain counts the workspace has room for. */
+int st_batch_tune(st_batch* batch, void* stream, int reps);
+
+/* Current configuration; any output pointer may be NULL.  best_ms is the tuned
+ * time per launch (0 before st_batch_tune). */
+int st_batch_config(const st_batch* batch, int* lanes, int* use_graph, int64_t* grad_min_blocks,
+                    int64_t* strided_min_waves, double* best_ms);
+
+/* Releases the batch (waits for its work to finish). */
+int st_batch_destroy(st_batch* batch);
 
 /*
  * Kernel timing for measurement tools.  While enabled, every kernel launched

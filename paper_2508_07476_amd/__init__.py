@@ -7,6 +7,9 @@ thin Python binding.  Building: ``python -m paper_2508_07476_amd.csrc.build``.
 
 from ._binding import (  # noqa: F401
     ALL_OUTPUTS,
+    ST_BATCH_MAX_LANES,
+    Batch,
+    StChunk,
     LIB_PATH,
     ST_DTYPE_F32,
     ST_DTYPE_U16,

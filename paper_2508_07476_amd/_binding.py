@@ -25,6 +25,18 @@ ST_FLAG_DEGENERATE = 1
 ST_FLAG_OUTSIDE_MASK = 2
 ST_FLAG_ON_AXIS = 4
 
+ST_BATCH_MAX_LANES = 8
+
+
+class StChunk(ctypes.Structure):
+    """Mirror of ``st_chunk`` (include/st.h)."""
+    _fields_ = [("volume", ctypes.c_void_p), ("dtype", ctypes.c_int), ("mask", ctypes.c_void_p),
+                ("nz", ctypes.c_int64), ("ny", ctypes.c_int64), ("nx", ctypes.c_int64),
+                ("rho", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("e3", ctypes.c_void_p), ("evals", ctypes.c_void_p), ("fa", ctypes.c_void_p),
+                ("ha", ctypes.c_void_p), ("ia", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
 # exported symbols and their C signatures (restype, argtypes)
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -41,6 +53,14 @@ SIGNATURES = {
     "st_angles": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _DP, _DP, _P, _P, _P, _P]),
     "st_surrogate_infer": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _SZ, _D,
                                           _D, _D, _D, _DP, _DP, _P, _P, _P, _P, _P, _P]),
+    "st_batch_workspace_bytes": (_SZ, [ctypes.POINTER(StChunk), ctypes.c_int, ctypes.c_int]),
+    "st_batch_create": (ctypes.c_int, [ctypes.POINTER(StChunk), ctypes.c_int, _D, _D, _DP, _DP,
+                                       ctypes.c_int, _P, _SZ, ctypes.POINTER(_P)]),
+    "st_batch_launch": (ctypes.c_int, [_P, _P]),
+    "st_batch_tune": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "st_batch_config": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
+    "st_batch_destroy": (ctypes.c_int, [_P]),
     "st_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "st_profile_reset": (ctypes.c_int, []),
     "st_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, _SZ, _DP,
@@ -243,3 +263,112 @@ def profile_read() -> dict:
         lib.st_profile_read(i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt))
         out[buf.value.decode()] = (ms.value, cnt.value)
     return out
+
+
+class Batch:
+    """A batch of independent volumes (e.g. halo-padded chunks of one scan) run
+    through the st_compute path as one captured, replayable unit (``st_batch_*``).
+
+    ``chunks``: sequence of dicts with ``volume`` (3-D uint16/float32 CUDA
+    tensor), ``rho``, optional ``origin`` (z, y, x) of ``volume[0, 0, 0]`` in the
+    axis' coordinates (default 0) and optional ``mask``.  Outputs (``outputs``
+    names) are allocated here and returned per chunk by :attr:`results`.
+    ``lanes`` 0 leaves the chain count to :meth:`tune`.
+    """
+
+    def __init__(self, chunks, sigma: float, truncate: float = 4.0, axis_center=None,
+                 axis_direction=None, outputs: Iterable[str] = ("e3", "fa", "ha", "ia", "flags"),
+                 lanes: int = 0, workspace=None):
+        import torch
+        lib = load_library()
+        outputs = tuple(outputs)
+        for k in outputs:
+            if k not in ALL_OUTPUTS:
+                raise ValueError(f"unknown output {k!r}")
+        n = len(chunks)
+        if n < 1:
+            raise ValueError("need at least one chunk")
+        arr = (StChunk * n)()
+        self._keep = []
+        self.results = []
+        dev = None
+        for i, c in enumerate(chunks):
+            vol = c["volume"]
+            _require_device_tensor(f"chunks[{i}].volume", vol, (torch.uint16, torch.float32))
+            if vol.dim() != 3:
+                raise ValueError("chunk volumes must be 3-D (nz, ny, nx)")
+            dev = vol.device if dev is None else dev
+            if vol.device != dev:
+                raise ValueError("all chunks must be on one device")
+            nz, ny, nx = vol.shape
+            mask = c.get("mask")
+            if mask is not None:
+                _require_device_tensor(f"chunks[{i}].mask", mask, (torch.uint8, torch.bool), (nz, ny, nx))
+                if mask.dtype == torch.bool:
+                    mask = mask.view(torch.uint8)
+            res = {}
+            for k in outputs:
+                shape = (3, nz, ny, nx) if k in ("e3", "evals") else (nz, ny, nx)
+                res[k] = torch.empty(shape, dtype=torch.uint8 if k == "flags" else torch.float32,
+                                     device=dev)
+            self.results.append(res)
+            self._keep += [vol, mask]
+            org = c.get("origin", (0.0, 0.0, 0.0))
+            arr[i] = StChunk(vol.data_ptr(), ST_DTYPE_U16 if vol.dtype == torch.uint16 else ST_DTYPE_F32,
+                             _ptr(mask), nz, ny, nx, float(c["rho"]), (ctypes.c_double * 3)(*map(float, org)),
+                             _ptr(res.get("e3")), _ptr(res.get("evals")), _ptr(res.get("fa")),
+                             _ptr(res.get("ha")), _ptr(res.get("ia")), _ptr(res.get("flags")))
+        self.device = dev
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            _require_device_tensor("workspace", workspace, (torch.uint8,))
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+            self._keep.append(workspace)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            code = lib.st_batch_create(arr, n, float(sigma), float(truncate), _vec3(axis_center),
+                                       _vec3(axis_direction), int(lanes), ws_ptr, ws_bytes,
+                                       ctypes.byref(handle))
+        _check(code)
+        self._h = handle
+
+    @staticmethod
+    def workspace_bytes(shapes, lanes: int = 0) -> int:
+        """Workspace a batch of volumes of these (nz, ny, nx) shapes needs."""
+        arr = (StChunk * len(shapes))()
+        for i, (nz, ny, nx) in enumerate(shapes):
+            arr[i].nz, arr[i].ny, arr[i].nx = int(nz), int(ny), int(nx)
+        return load_library().st_batch_workspace_bytes(arr, len(shapes), int(lanes))
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("batch is closed")
+        return self._h
+
+    def launch(self):
+        """Enqueue the batch on the device's current stream."""
+        _check(load_library().st_batch_launch(self._handle(), _stream_handle(self.device)))
+
+    def tune(self, reps: int = 2) -> dict:
+        """Autotune the launch configuration on the real chunks (synchronises)."""
+        _check(load_library().st_batch_tune(self._handle(), _stream_handle(self.device), int(reps)))
+        return self.config()
+
+    def config(self) -> dict:
+        lanes, graph = ctypes.c_int(), ctypes.c_int()
+        gb, sw, ms = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(load_library().st_batch_config(self._handle(), ctypes.byref(lanes), ctypes.byref(graph),
+                                              ctypes.byref(gb), ctypes.byref(sw), ctypes.byref(ms)))
+        return {"lanes": lanes.value, "graph": bool(graph.value), "grad_min_blocks": gb.value,
+                "strided_min_waves": sw.value, "best_ms": ms.value}
+
+    def close(self):
+        if self._h is not None:
+            _check(load_library().st_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,11 +11,16 @@
 #include <string>
 #include <vector>
 
-#include "st_internal.h"
+#include "st_host.h"
 
 namespace {
-
 thread_local std::string g_error;
+}  // namespace
+
+namespace st {
+namespace host {
+
+void clear_error() { g_error.clear(); }
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -30,6 +35,14 @@ int fail(int code, const char* fmt, ...) {
 int device_fail(hipError_t e, const char* what) {
   return fail(ST_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace host
+}  // namespace st
+
+namespace {
+
+using st::host::device_fail;
+using st::host::fail;
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -167,25 +180,22 @@ hipError_t timed(const char* name, hipStream_t stream, F&& fn) {
 
 }  // namespace
 
-extern "C" {
+namespace st {
+namespace host {
 
-int st_version(void) { return 10000; }
+int check_device_buffer(const void* p, size_t bytes, const char* name) {
+  return check_buffer(p, bytes, name);
+}
 
-const char* st_last_error(void) { return g_error.c_str(); }
-
-int st_filter_radius(double scale, double truncate) { return radius_of(scale, truncate); }
-
-size_t st_workspace_bytes(int64_t nz, int64_t ny, int64_t nx) {
-  int64_t n;
-  if (!checked_count(nz, ny, nx, &n)) return 0;
+size_t path_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
   return 12 * plane_bytes(n);
 }
 
-int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, int64_t ny,
-               int64_t nx, double sigma, double rho, double truncate, const double* axis_center,
-               const double* axis_direction, float* e3, float* evals, float* fa, float* ha,
-               float* ia, uint8_t* flags, void* workspace, size_t workspace_bytes, void* stream_) {
-  g_error.clear();
+int prepare_path(PathArgs& a, const void* volume, int dtype, const uint8_t* mask, int64_t nz,
+                 int64_t ny, int64_t nx, double sigma, double rho, double truncate,
+                 const double* axis_center, const double* axis_direction, float* e3, float* evals,
+                 float* fa, float* ha, float* ia, uint8_t* flags) {
   // ---- host-only validation (no HIP call before it passes) ----
   if (volume == nullptr) return fail(ST_ERR_INVALID_ARG, "volume is NULL");
   if (dtype != ST_DTYPE_U16 && dtype != ST_DTYPE_F32)
@@ -210,43 +220,54 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
     return fail(ST_ERR_INVALID_ARG, "ha / ia need an axis (axis_center and axis_direction)");
   if (!e3 && !evals && !fa && !ha && !ia && !flags)
     return fail(ST_ERR_INVALID_ARG, "no output requested");
-  const size_t ws_need = 12 * plane_bytes(n);
-  if (workspace == nullptr && workspace_bytes != 0)
-    return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
-  if (workspace != nullptr && workspace_bytes < ws_need)
-    return fail(ST_ERR_INVALID_ARG, "workspace_bytes %zu < required %zu", workspace_bytes, ws_need);
 
-  // ---- device buffer checks ----
-  const size_t N = static_cast<size_t>(n);
-  const size_t esz = dtype == ST_DTYPE_U16 ? 2 : 4;
-  if ((st = check_buffer(volume, N * esz, "volume")) != ST_OK) return st;
-  if ((st = check_buffer(mask, N, "mask")) != ST_OK) return st;
-  if ((st = check_buffer(e3, 3 * N * 4, "e3")) != ST_OK) return st;
-  if ((st = check_buffer(evals, 3 * N * 4, "evals")) != ST_OK) return st;
-  if ((st = check_buffer(fa, N * 4, "fa")) != ST_OK) return st;
-  if ((st = check_buffer(ha, N * 4, "ha")) != ST_OK) return st;
-  if ((st = check_buffer(ia, N * 4, "ia")) != ST_OK) return st;
-  if ((st = check_buffer(flags, N, "flags")) != ST_OK) return st;
-  if ((st = check_buffer(workspace, ws_need, "workspace")) != ST_OK) return st;
-  if ((reinterpret_cast<uintptr_t>(volume) % esz) != 0)
+  a.volume = volume; a.dtype = dtype; a.mask = mask;
+  a.nz = nz; a.ny = ny; a.nx = nx; a.n = n;
+  a.sigma = sigma; a.rho = rho; a.truncate = truncate;
+  a.has_axis = has_axis;
+  for (int i = 0; i < 3; ++i) {
+    a.center[i] = has_axis ? axis_center[i] : 0.0;
+    a.unit[i] = unit[i];
+  }
+  a.e3 = e3; a.evals = evals; a.fa = fa; a.ha = ha; a.ia = ia; a.flags = flags;
+  return ST_OK;
+}
+
+int check_path_buffers(const PathArgs& a) {
+  const size_t N = static_cast<size_t>(a.n);
+  const size_t esz = a.dtype == ST_DTYPE_U16 ? 2 : 4;
+  int st;
+  if ((st = check_buffer(a.volume, N * esz, "volume")) != ST_OK) return st;
+  if ((st = check_buffer(a.mask, N, "mask")) != ST_OK) return st;
+  if ((st = check_buffer(a.e3, 3 * N * 4, "e3")) != ST_OK) return st;
+  if ((st = check_buffer(a.evals, 3 * N * 4, "evals")) != ST_OK) return st;
+  if ((st = check_buffer(a.fa, N * 4, "fa")) != ST_OK) return st;
+  if ((st = check_buffer(a.ha, N * 4, "ha")) != ST_OK) return st;
+  if ((st = check_buffer(a.ia, N * 4, "ia")) != ST_OK) return st;
+  if ((st = check_buffer(a.flags, N, "flags")) != ST_OK) return st;
+  if ((reinterpret_cast<uintptr_t>(a.volume) % esz) != 0)
     return fail(ST_ERR_INVALID_ARG, "volume is not aligned to its element size");
-  for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
-                        static_cast<const void*>(fa), static_cast<const void*>(ha),
-                        static_cast<const void*>(ia)})
+  for (const void* q : {static_cast<const void*>(a.e3), static_cast<const void*>(a.evals),
+                        static_cast<const void*>(a.fa), static_cast<const void*>(a.ha),
+                        static_cast<const void*>(a.ia)})
     if (q && (reinterpret_cast<uintptr_t>(q) % 4) != 0)
       return fail(ST_ERR_INVALID_ARG, "float outputs must be 4-byte aligned");
+  return ST_OK;
+}
 
-  hipStream_t stream = static_cast<hipStream_t>(stream_);
-  char* ws = static_cast<char*>(workspace);
-  bool owned = false;
-  if (ws == nullptr) {
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), ws_need, stream);
-    if (e != hipSuccess || ws == nullptr) {
-      (void)hipGetLastError();
-      return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) failed: %s", ws_need, hipGetErrorString(e));
-    }
-    owned = true;
-  }
+hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const LaunchShape& shape,
+                        bool profile, const char** stage_out) {
+  const void* volume = a.volume;
+  const int dtype = a.dtype;
+  const uint8_t* mask = a.mask;
+  const int64_t nz = a.nz, ny = a.ny, nx = a.nx, n = a.n;
+  float* e3 = a.e3; float* evals = a.evals; float* fa = a.fa; float* ha = a.ha; float* ia = a.ia;
+  uint8_t* flags = a.flags;
+  const bool has_axis = a.has_axis;
+  const int rs = radius_of(a.sigma, a.truncate), rr = radius_of(a.rho, a.truncate);
+  auto timed = [&](const char* name, hipStream_t s, auto&& fn) -> hipError_t {
+    return profile ? ::timed(name, s, fn) : fn();
+  };
   const size_t pb = plane_bytes(n);
   float* A[6];
   float* B[6];
@@ -258,8 +279,8 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
   // compiled radii: the next one up, taps zero-padded
   const int ps = st::padded_radius(rs, true), pr = st::padded_radius(rr, false);
   st::Taps gs, ds, gr;
-  make_taps(sigma, rs, ps, gs, &ds);
-  make_taps(rho, rr, pr, gr, nullptr);
+  make_taps(a.sigma, rs, ps, gs, &ds);
+  make_taps(a.rho, rr, pr, gr, nullptr);
 
   auto strided = [&](bool zaxis, int njobs, const st::StridedJob* jobs, int R, int in_dtype,
                      bool with_d, const st::Taps& wg, const st::Taps* wd) {
@@ -279,7 +300,8 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
     const int64_t waves = p.x_tiles * p.n_other * njobs;
     int nchunks = 1;
     const int64_t min_chunk = std::max<int64_t>(64, 4 * R);
-    while (waves * nchunks < 16384 && (p.n_axis + 2 * nchunks - 1) / (2 * nchunks) >= min_chunk)
+    while (waves * nchunks < shape.strided_min_waves &&
+           (p.n_axis + 2 * nchunks - 1) / (2 * nchunks) >= min_chunk)
       nchunks *= 2;
     p.nchunks = nchunks;
     p.chunk = (p.n_axis + nchunks - 1) / nchunks;
@@ -305,7 +327,7 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
       p.y_tiles = (ny + st::kGradTY - 1) / st::kGradTY;
       // split z until there are enough blocks to fill the chip, keeping chunks >= 8R
       int64_t nch = 1;
-      while (p.x_tiles * p.y_tiles * nch < 4096 && nz / (2 * nch) >= 8 * ps) nch *= 2;
+      while (p.x_tiles * p.y_tiles * nch < shape.grad_min_blocks && nz / (2 * nch) >= 8 * ps) nch *= 2;
       p.chunk = (nz + nch - 1) / nch;
       p.nchunks = static_cast<int>((nz + p.chunk - 1) / p.chunk);
       p.wg = gs; p.wd = ds;
@@ -370,7 +392,7 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
       p.vec_ok = vec;
       p.has_axis = has_axis;
       if (has_axis)
-        for (int i = 0; i < 3; ++i) { p.center[i] = axis_center[i]; p.dir[i] = unit[i]; }
+        for (int i = 0; i < 3; ++i) { p.center[i] = a.center[i]; p.dir[i] = a.unit[i]; }
       p.w = gr;
       stage = "integrate_x_eigen";
       e = timed("integrate_x_eigen", stream, [&] { return st::launch_xfinal(pr, p, stream); });
@@ -378,6 +400,57 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
     }
   } while (false);
 
+  *stage_out = stage;
+  return e;
+}
+
+}  // namespace host
+}  // namespace st
+
+extern "C" {
+
+int st_version(void) { return 10000; }
+
+const char* st_last_error(void) { return g_error.c_str(); }
+
+int st_filter_radius(double scale, double truncate) { return radius_of(scale, truncate); }
+
+size_t st_workspace_bytes(int64_t nz, int64_t ny, int64_t nx) {
+  int64_t n;
+  if (!checked_count(nz, ny, nx, &n)) return 0;
+  return 12 * plane_bytes(n);
+}
+
+int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, int64_t ny,
+               int64_t nx, double sigma, double rho, double truncate, const double* axis_center,
+               const double* axis_direction, float* e3, float* evals, float* fa, float* ha,
+               float* ia, uint8_t* flags, void* workspace, size_t workspace_bytes, void* stream_) {
+  g_error.clear();
+  st::host::PathArgs a;
+  int st = st::host::prepare_path(a, volume, dtype, mask, nz, ny, nx, sigma, rho, truncate,
+                                  axis_center, axis_direction, e3, evals, fa, ha, ia, flags);
+  if (st != ST_OK) return st;
+  const size_t ws_need = st::host::path_workspace_bytes(a.n);
+  if (workspace == nullptr && workspace_bytes != 0)
+    return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
+  if (workspace != nullptr && workspace_bytes < ws_need)
+    return fail(ST_ERR_INVALID_ARG, "workspace_bytes %zu < required %zu", workspace_bytes, ws_need);
+  if ((st = st::host::check_path_buffers(a)) != ST_OK) return st;
+  if ((st = check_buffer(workspace, ws_need, "workspace")) != ST_OK) return st;
+
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  bool owned = false;
+  if (ws == nullptr) {
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), ws_need, stream);
+    if (e != hipSuccess || ws == nullptr) {
+      (void)hipGetLastError();
+      return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) failed: %s", ws_need, hipGetErrorString(e));
+    }
+    owned = true;
+  }
+  const char* stage = "";
+  hipError_t e = st::host::enqueue_path(a, ws, stream, st::host::LaunchShape{}, true, &stage);
   if (owned) {
     hipError_t f = hipFreeAsync(ws, stream);
     if (e == hipSuccess && f != hipSuccess) { e = f; stage = "hipFreeAsync"; }

@@ -1,0 +1,71 @@
+// Host-side pieces shared by the single-volume entry points and the chunk
+// batch: error reporting, argument validation and the pass sequence.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "st_internal.h"
+
+namespace st {
+namespace host {
+
+// Sets the thread-local message returned by st_last_error() and returns `code`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int device_fail(hipError_t e, const char* what);
+void clear_error();
+
+// One volume through the whole path, validated.
+struct PathArgs {
+  const void* volume;
+  int dtype;
+  const uint8_t* mask;
+  int64_t nz, ny, nx, n;
+  double sigma, rho, truncate;
+  bool has_axis;
+  double center[3];  // axis point in this volume's own voxel coordinates (z, y, x)
+  double unit[3];    // unit axis direction (z, y, x)
+  float* e3;
+  float* evals;
+  float* fa;
+  float* ha;
+  float* ia;
+  uint8_t* flags;
+};
+
+// Launch shapes: how far each pass splits its filtered axis to fill the chip.
+// The gradient pass splits z until it has at least grad_min_blocks blocks; the
+// strided passes split until they have at least strided_min_waves waves (in
+// both cases only while the pieces stay long against the filter radius).
+struct LaunchShape {
+  int64_t grad_min_blocks = 4096;
+  int64_t strided_min_waves = 16384;
+};
+
+// Host-only validation of one volume's arguments (no HIP call); fills `a`.
+// Returns ST_OK or an error code with the message set.
+int prepare_path(PathArgs& a, const void* volume, int dtype, const uint8_t* mask, int64_t nz,
+                 int64_t ny, int64_t nx, double sigma, double rho, double truncate,
+                 const double* axis_center, const double* axis_direction, float* e3, float* evals,
+                 float* fa, float* ha, float* ia, uint8_t* flags);
+
+// The buffer [p, p + bytes) lies inside one device allocation (p NULL: ST_OK).
+int check_device_buffer(const void* p, size_t bytes, const char* name);
+
+// Every non-NULL buffer of `a` lies inside one device allocation of the size
+// the path reads or writes, and is aligned to its element size.
+int check_path_buffers(const PathArgs& a);
+
+// Workspace bytes of the pass sequence for n voxels (12 float planes, each
+// 256-byte aligned); 0 if n is out of range.
+size_t path_workspace_bytes(int64_t n);
+
+// Enqueues the pass sequence of `a` on `stream` with workspace `ws`.  With
+// `profile`, each launch is bracketed by the library's timing events (when
+// profiling is enabled).  On failure returns the HIP error and names the pass
+// in *stage.
+hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const LaunchShape& shape,
+                        bool profile, const char** stage);
+
+}  // namespace host
+}  // namespace st

@@ -173,3 +173,23 @@ def cylindrical_radius(spec: PhantomSpec, shape: Optional[Sequence[int]] = None,
     y = torch.arange(origin[1], origin[1] + ny, dtype=torch.float64).view(1, ny, 1) - cy
     x = torch.arange(origin[2], origin[2] + nx, dtype=torch.float64).view(1, 1, nx) - cx
     return torch.sqrt(y * y + x * x)
+
+
+def batch_crops(volume_shape=(512, 512, 512), n: int = 200, seed: int = 4, inner=(64, 384),
+                rhos=(2.0, 3.0, 4.0), halo_per_rho: float = 3.0):
+    """Uneven halo-padded chunks of one volume: for each of ``n`` chunks an
+    integration scale rho drawn from ``rhos``, interior sides drawn uniformly
+    from [inner[0], inner[1]] per axis, a halo of round(halo_per_rho * rho) on
+    every side, and a uniform position where the padded chunk fits.  Returns a
+    list of ((z, y, x) origin, (nz, ny, nx) padded shape, rho)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        rho = float(rng.choice(rhos))
+        h = int(round(halo_per_rho * rho))
+        shp = tuple(int(s) + 2 * h for s in rng.integers(inner[0], inner[1] + 1, size=3))
+        org = tuple(int(rng.integers(0, volume_shape[d] - shp[d] + 1)) for d in range(3))
+        out.append((org, shp, rho))
+    return out

@@ -113,3 +113,64 @@ def test_error_message_is_per_call(lib):
     assert "dtype" in lib.st_last_error().decode()
     _compute(lib, nz=0)
     assert "dtype" not in lib.st_last_error().decode()
+
+
+def _chunks(*specs):
+    arr = (B.StChunk * max(1, len(specs)))()
+    for i, s in enumerate(specs):
+        c = dict(volume=FAKE.value, dtype=B.ST_DTYPE_U16, nz=8, ny=8, nx=8, rho=2.0, e3=FAKE.value)
+        c.update(s)
+        arr[i].volume, arr[i].dtype = c["volume"], c["dtype"]
+        arr[i].nz, arr[i].ny, arr[i].nx, arr[i].rho = c["nz"], c["ny"], c["nx"], c["rho"]
+        arr[i].e3, arr[i].ha = c["e3"], c.get("ha")
+    return arr
+
+
+def test_batch_workspace_bytes(lib):
+    plane = lambda n: ((n * 4 + 255) // 256) * 256  # noqa: E731
+    arr = _chunks(dict(nz=5, ny=7, nx=9), dict(nz=10, ny=3, nx=4))
+    slot = 12 * max(plane(5 * 7 * 9), plane(10 * 3 * 4))
+    assert lib.st_batch_workspace_bytes(arr, 2, 3) == 3 * slot
+    assert lib.st_batch_workspace_bytes(arr, 2, 0) == B.ST_BATCH_MAX_LANES * slot
+    assert lib.st_batch_workspace_bytes(arr, 2, 9) == 0
+    assert lib.st_batch_workspace_bytes(arr, 0, 1) == 0
+    assert lib.st_batch_workspace_bytes(_chunks(dict(nz=0)), 1, 1) == 0
+    assert st.Batch.workspace_bytes([(5, 7, 9), (10, 3, 4)], lanes=3) == 3 * slot
+
+
+def _create(lib, arr, n, lanes=1, center=None, direction=None, ws=None, ws_bytes=0, out=True):
+    vec = lambda v: None if v is None else (ctypes.c_double * 3)(*v)  # noqa: E731
+    h = ctypes.c_void_p()
+    code = lib.st_batch_create(arr, n, 1.0, 4.0, vec(center), vec(direction), lanes, ws, ws_bytes,
+                               ctypes.byref(h) if out else None)
+    assert not h.value  # nothing is created when validation fails
+    return code, lib.st_last_error().decode()
+
+
+@pytest.mark.parametrize("case,text", [
+    (dict(out=False), "out is NULL"),
+    (dict(n=0), "at least one chunk"),
+    (dict(lanes=9), "lanes"),
+    (dict(lanes=-1), "lanes"),
+    (dict(center=(1, 2, 3)), "both"),
+    (dict(specs=[{}, dict(rho=0.0)]), "chunk 1"),
+    (dict(specs=[dict(nx=0)]), "sizes"),
+    (dict(specs=[dict(dtype=5)]), "dtype"),
+    (dict(specs=[dict(ha=FAKE.value)]), "need an axis"),
+    (dict(specs=[dict(e3=None)]), "no output"),
+    (dict(ws_bytes=64), "workspace is NULL"),
+    (dict(ws=FAKE, ws_bytes=64), "workspace_bytes"),
+])
+def test_batch_create_rejects_invalid_arguments_on_host(lib, case, text):
+    specs = case.pop("specs", [{}])
+    n = case.pop("n", len(specs))
+    code, msg = _create(lib, _chunks(*specs), n, **case)
+    assert code == B.ST_ERR_INVALID_ARG, msg
+    assert text in msg
+
+
+def test_batch_calls_reject_null_handle(lib):
+    assert lib.st_batch_launch(None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_batch_tune(None, None, 1) == B.ST_ERR_INVALID_ARG
+    assert lib.st_batch_config(None, None, None, None, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_batch_destroy(None) == B.ST_OK

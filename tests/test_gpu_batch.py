@@ -1,0 +1,120 @@
+"""Chunk batches on the GPU (MI355X only).
+
+A batch of uneven crops of one uint16 phantom (with mask and axis), mixed
+integration scales rho in {2, 3, 4}, one crop thinner than its filter radius:
+every chunk's outputs equal, bitwise, those of st_compute on the same crop, and
+match the FP64 oracle run on the crop (each crop is its own volume, reflected at
+its faces; its origin places it in the axis' frame).  Graph replays with eager
+work in between, direct multi-stream enqueue and every autotuned configuration
+give the same bits.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2508_07476_amd as st
+from phantom import helix
+
+from _parity import assert_parity, compare, summary
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SIGMA = 1.0
+OUTS = ("e3", "evals", "fa", "ha", "ia", "flags")
+# (origin (z, y, x), shape, rho)
+CROPS = [((10, 20, 30), (40, 52, 36), 2.0), ((0, 0, 0), (64, 40, 48), 3.0),
+         ((30, 5, 8), (33, 47, 70), 4.0), ((20, 30, 2), (50, 50, 50), 2.0),
+         ((60, 40, 10), (28, 60, 44), 3.0), ((5, 60, 40), (72, 33, 29), 4.0),
+         ((40, 70, 90), (12, 9, 35), 4.0)]
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def phantom():
+    spec = helix.PhantomSpec(shape=(96, 112, 128), annuli=(helix.Annulus(16.0, 44.0),), period=4.0,
+                             noise=(0.05,), dtype="u16", seed=4, with_mask=True)
+    ph = helix.generate(spec)
+    return ph
+
+
+def _crop(t, org, shp):
+    return t[org[0]:org[0] + shp[0], org[1]:org[1] + shp[1], org[2]:org[2] + shp[2]].contiguous()
+
+
+def _chunks(ph):
+    out = []
+    for i, (org, shp, rho) in enumerate(CROPS):
+        c = {"volume": _crop(ph["volume"], org, shp).to(DEV), "rho": rho, "origin": org}
+        if i % 2 == 0:
+            c["mask"] = _crop(ph["mask"], org, shp).to(DEV)
+        out.append(c)
+    return out
+
+
+def _snapshot(batch):
+    torch.cuda.synchronize()
+    return [{k: v.clone() for k, v in r.items()} for r in batch.results]
+
+
+def _same(a, b):
+    return all(torch.equal(x[k], y[k]) for x, y in zip(a, b) for k in x)
+
+
+def test_batch_matches_single_calls_and_oracle(phantom):
+    chunks = _chunks(phantom)
+    _log("case: batch of", len(chunks), "chunks, lanes=3")
+    b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                 outputs=OUTS, lanes=3)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (c, res) in enumerate(zip(chunks, b.results)):
+        org, shp, rho = CROPS[i]
+        center = [phantom["center"][d] - org[d] for d in range(3)]
+        single = st.st_compute(c["volume"], SIGMA, rho, mask=c.get("mask"), axis_center=center,
+                               axis_direction=phantom["direction"], outputs=OUTS)
+        torch.cuda.synchronize()
+        for k in OUTS:
+            assert torch.equal(res[k], single[k]), (i, k)
+        g = {k: v.cpu().numpy() for k, v in res.items()}
+        o = oracle.compute(c["volume"].cpu().numpy(), None if "mask" not in c else c["mask"].cpu().numpy(),
+                           SIGMA, rho, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                           origin=org)
+        stats = compare(g, o, shp, phantom["center"], phantom["direction"], origin=org)
+        _log(f"chunk {i} {shp} rho {rho}:", summary(stats))
+        assert_parity(stats, f"chunk {i}")
+    b.close()
+
+
+def test_batch_replays_tuning_and_direct_enqueue_are_bitwise_stable(phantom):
+    chunks = _chunks(phantom)
+    b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                 outputs=OUTS, lanes=0)
+    _log("case: lanes=0 batch, initial config", b.config())
+    b.launch()
+    ref = _snapshot(b)
+    for rep in range(3):  # replays with eager work (clearing the outputs) in between
+        for r in b.results:
+            for v in r.values():
+                v.zero_()
+        torch.cuda.synchronize()
+        b.launch()
+        assert _same(_snapshot(b), ref), rep
+    cfg = b.tune(reps=1)
+    _log("tuned config", cfg)
+    # the last configuration the tuner ran is direct multi-stream enqueue
+    assert _same(_snapshot(b), ref)
+    assert 1 <= cfg["lanes"] <= st.ST_BATCH_MAX_LANES and cfg["best_ms"] > 0
+    for r in b.results:
+        for v in r.values():
+            v.zero_()
+    b.launch()
+    assert _same(_snapshot(b), ref)
+    b.close()
