@@ -20,6 +20,7 @@ tensor    gradients at sigma, outer products, integration at rho
 eigen     sorted eigen-pairs (LAPACK), cyclic Jacobi cross-check, FA, degeneracy
 angles    cylindrical frame about the given axis, HA and IA
 pipeline  the whole path on one volume (or one padded block) -> every output map
+surrogate forward pass of the learned orientation surrogate (a dense 3-D CNN)
 
 Parity pins: every function is pinned by the ``-m "not gpu"`` tests
 (brute-force 3-D correlation, SciPy's ``gaussian_filter``, closed forms,
@@ -38,3 +39,4 @@ from .angles import cylindrical_frame, helix_intrusion, ON_AXIS_RADIUS  # noqa: 
 from .pipeline import (  # noqa: F401
     compute, FLAG_DEGENERATE, FLAG_OUTSIDE_MASK, FLAG_ON_AXIS,
 )
+from . import surrogate  # noqa: F401
