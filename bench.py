@@ -111,6 +111,75 @@ def cpu_baseline(vol_u16, mask_u8, center, direction):
                       f"(tensor, eigen, FA, HA, IA) in FP64 NumPy, {nvox} voxels in {wall:.1f} s"}
 
 
+SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2508_07476_amd", "surrogate_weights.npy")
+
+
+def run_surrogate(args, torch, st, helix, dev):
+    """Surrogate-only and with fallback (confidence < 0.9 takes the structure-tensor
+    result) against the plain path on the 512^3 headline volume: throughput and the
+    fibre-angle error w.r.t. the plain path inside the mask, non-degenerate voxels."""
+    import numpy as np
+    blob = np.load(args.weights or SURROGATE_WEIGHTS, allow_pickle=False).astype(np.float32)
+    w = torch.from_numpy(blob).to(dev)
+    spec = helix.spec_headline_u16(shape=SHAPE)
+    ph = helix.generate(spec, device=dev)
+    vol, mask = ph["volume"], ph["mask"]
+    nvox = vol.numel()
+    kw = dict(mask=mask, axis_center=ph["center"], axis_direction=ph["direction"])
+    plain = st.st_compute(vol, SIGMA, RHO, TRUNCATE, outputs=("e3", "fa", "flags"), **kw)
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        st.profile_reset()
+        st.profile_enable(True)
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        st.profile_enable(False)
+        kern = {k: round(v[0] / v[1], 4) for k, v in st.profile_read().items()}
+        return ev[0].elapsed_time(ev[1]) / args.steps, kern
+
+    outs = ("e3", "fa", "ha", "ia", "confidence")
+    sur = {}
+    res = {}
+    for name, thr in (("surrogate", 0.0), ("fallback_0.9", 0.9)):
+        out = {}
+        ms, kern = timed(lambda: out.update(st.st_surrogate_infer(vol, w, thr, SIGMA, RHO, TRUNCATE,
+                                                                  outputs=outs, **kw)))
+        sel = (plain["flags"] == 0)
+        a = out["e3"][:, sel].double()
+        b = plain["e3"][:, sel].double()
+        ang = torch.rad2deg(torch.atan2(torch.linalg.cross(a, b, dim=0).norm(dim=0), (a * b).sum(0).abs()))
+        q = torch.quantile(ang[::max(1, ang.numel() // 5_000_000)], torch.tensor([0.5, 0.9], device=dev,
+                                                                                 dtype=ang.dtype))
+        fell = float(((out["confidence"] < thr) & (mask != 0)).sum()) / float((mask != 0).sum()) if thr else 0.0
+        res[name] = {"ms_per_step": round(ms, 4), "value": round(nvox / ms / 1e6, 4), "unit": "Gvoxels/s",
+                     "median_angle_deg": round(float(q[0]), 3), "p90_angle_deg": round(float(q[1]), 3),
+                     "frac_within_2deg": round(float((ang <= 2.0).double().mean()), 4),
+                     "fallback_fraction": round(fell, 4), "kernels": kern}
+        sur = out
+    del sur
+    pms, pkern = timed(lambda: st.st_compute(vol, SIGMA, RHO, TRUNCATE, outputs=("e3", "fa", "ha", "ia"), **kw))
+    line = {
+        "metric": METRIC, "value": res["surrogate"]["value"], "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["surrogate"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "512^3 uint16 helical rod-lattice phantom + annulus mask; learned surrogate "
+                               "(5x 3x3x3 conv, 32 ch, bf16 MFMA) vs structure-tensor path sigma=1.5, rho=4",
+                   "weights": os.path.basename(args.weights or SURROGATE_WEIGHTS)},
+        "surrogate": res["surrogate"], "surrogate_with_fallback": res["fallback_0.9"],
+        "plain": {"ms_per_step": round(pms, 4), "value": round(nvox / pms / 1e6, 4), "unit": "Gvoxels/s"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 BATCH_SIGMA = 1.0
 BATCH_OUTPUTS = ("e3", "fa", "ha", "ia", "flags")
 
@@ -190,6 +259,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="time the learned surrogate (bf16 3-D CNN) on the headline volume and "
+                         "report its fibre-angle error against the structure-tensor path")
+    ap.add_argument("--weights", default=None, help="surrogate weights (.npy, float32 blob)")
     ap.add_argument("--batch", action="store_true",
                     help="time the chunk-batch workload (200 uneven halo-padded uint16 crops of the "
                          "512^3 phantom, rho in {2,3,4}, sigma 1) instead of the headline volume")
@@ -219,6 +292,8 @@ def main():
     st.load_library()
     if args.batch:
         return run_batch(args, torch, st, helix, dev)
+    if args.surrogate:
+        return run_surrogate(args, torch, st, helix, dev)
     spec = helix.spec_headline_u16(shape=SHAPE)
     ph = helix.generate(spec, device=dev)
     vol, mask = ph["volume"], ph["mask"]

@@ -134,10 +134,35 @@ int st_angles(const float* e3, const uint8_t* mask,
               float* ha, float* ia, uint8_t* flags, void* stream);
 
 /*
- * st_surrogate_infer -- learned fibre-orientation surrogate with fallback to
- * st_compute where its confidence is below `min_confidence`.  Not provided by
- * this build: validates nothing and returns ST_ERR_UNSUPPORTED.
+ * st_surrogate_infer -- learned orientation surrogate with fallback.  Not a
+ * method of the paper: a dense 3-D CNN trained to approximate the fibre
+ * direction and FA that st_compute derives from the structure tensor (the
+ * orientation output of Figure 1(b)), evaluated on the bf16 matrix cores.
+ *
+ * Network (weights blob: ST_SURROGATE_WEIGHTS float32 values, in this order:
+ * in_scale, in_offset; W1 [32][1][27], b1 [32]; W2..W5 [32][32][27], b [32]
+ * each; Wh [5][32], bh [5]; tap t = 9 (dz+1) + 3 (dy+1) + (dx+1)):
+ *   x0 = bf16(v * in_scale + in_offset)
+ *   x_l = relu(b_l + sum_{c,t} bf16(W_l)[:, c, t] x_{l-1}[c, p + off(t)]), l = 1..5,
+ *         3x3x3 correlation with indices clamped at every face, float32
+ *         accumulation, rounded to bf16 for l < 5
+ *   h = bh + Wh x_5;  e3 = h[0:3]/|h[0:3]| with the canonical sign ((1,0,0)
+ *   when zero);  FA = sigmoid(h[3]);  confidence = sigmoid(h[4]).
+ *
+ *  volume, dtype, mask, nz, ny, nx, axis_center, axis_direction: as st_compute.
+ *  weights         DEVICE pointer to the float32 blob; weights_bytes >= 4 * ST_SURROGATE_WEIGHTS
+ *  min_confidence  in [0, 1]: inside the mask, voxels whose confidence is below
+ *                  it take st_compute's outputs (sigma, rho, truncate: as
+ *                  st_compute, validated only when min_confidence > 0; the
+ *                  structure-tensor path then runs on the whole volume)
+ *  e3 [3][N], fa, ha, ia, confidence [N]: DEVICE outputs, each may be NULL, at
+ *                  least one given; ha / ia need the axis.  Outside the mask
+ *                  every output is 0.  confidence is the surrogate's.
+ * Device workspace (128 bytes per voxel of activations, plus st_compute's
+ * workspace and 24 bytes per voxel with a fallback) is taken with
+ * hipMallocAsync on `stream` and released the same way.
  */
+#define ST_SURROGATE_WEIGHTS 111783
 int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
                        int64_t nz, int64_t ny, int64_t nx,
                        const void* weights, size_t weights_bytes, double min_confidence,

@@ -8,6 +8,8 @@ thin Python binding.  Building: ``python -m paper_2508_07476_amd.csrc.build``.
 from ._binding import (  # noqa: F401
     ALL_OUTPUTS,
     ST_BATCH_MAX_LANES,
+    ST_SURROGATE_WEIGHTS,
+    SURROGATE_OUTPUTS,
     Batch,
     StChunk,
     LIB_PATH,

@@ -233,12 +233,55 @@ def st_angles(e3, axis_center, axis_direction, mask=None, outputs: Iterable[str]
     return res
 
 
-def st_surrogate_infer(*args, **kwargs):
-    """The learned surrogate entry point; this build reports it as unsupported."""
+ST_SURROGATE_WEIGHTS = 111783
+SURROGATE_OUTPUTS = ("e3", "fa", "ha", "ia", "confidence")
+
+
+def st_surrogate_infer(volume, weights, min_confidence: float = 0.0, sigma: float = 1.5,
+                       rho: float = 4.0, truncate: float = 4.0, mask=None, axis_center=None,
+                       axis_direction=None, outputs: Iterable[str] = ("e3", "fa", "confidence"),
+                       out: Optional[dict] = None):
+    """Learned orientation surrogate (dense 3-D CNN on the bf16 matrix cores).
+
+    ``weights``: float32 CUDA tensor of ``ST_SURROGATE_WEIGHTS`` values (see
+    include/st.h for the layout).  Voxels inside the mask whose confidence is
+    below ``min_confidence`` take st_compute's outputs (sigma, rho, truncate).
+    Returns a dict of the requested outputs.
+    """
+    import torch
     lib = load_library()
-    code = lib.st_surrogate_infer(None, 0, None, 0, 0, 0, None, 0, 0.0, 0.0, 0.0, 0.0, None, None,
-                                  None, None, None, None, None, None)
+    _require_device_tensor("volume", volume, (torch.uint16, torch.float32))
+    if volume.dim() != 3:
+        raise ValueError("volume must be 3-D (nz, ny, nx)")
+    _require_device_tensor("weights", weights, (torch.float32,))
+    nz, ny, nx = volume.shape
+    dev = volume.device
+    if mask is not None:
+        _require_device_tensor("mask", mask, (torch.uint8, torch.bool), (nz, ny, nx))
+        if mask.dtype == torch.bool:
+            mask = mask.view(torch.uint8)
+    outputs = tuple(outputs)
+    for k in outputs:
+        if k not in SURROGATE_OUTPUTS:
+            raise ValueError(f"unknown output {k!r}")
+    out = out or {}
+    res = {}
+    for k in outputs:
+        shape = (3, nz, ny, nx) if k == "e3" else (nz, ny, nx)
+        if k in out:
+            _require_device_tensor(k, out[k], (torch.float32,), shape)
+            res[k] = out[k]
+        else:
+            res[k] = torch.empty(shape, dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        code = lib.st_surrogate_infer(_ptr(volume), ST_DTYPE_U16 if volume.dtype == torch.uint16 else ST_DTYPE_F32,
+                                      _ptr(mask), nz, ny, nx, _ptr(weights), weights.numel() * 4,
+                                      float(min_confidence), float(sigma), float(rho), float(truncate),
+                                      _vec3(axis_center), _vec3(axis_direction), _ptr(res.get("e3")),
+                                      _ptr(res.get("fa")), _ptr(res.get("ha")), _ptr(res.get("ia")),
+                                      _ptr(res.get("confidence")), _stream_handle(dev))
     _check(code)
+    return res
 
 
 def profile_enable(on: bool = True):

@@ -1,0 +1,314 @@
+// Learned orientation surrogate: a dense 3-D CNN (five 3x3x3 convolutions with
+// 32 channels and ReLU, a 1x1x1 head with 5 outputs) evaluated on the bf16
+// matrix cores, float32 accumulation.
+//
+// Activations are channel-last bf16 ([voxel][32], 64 bytes per voxel).  A
+// convolution is an implicit GEMM per tap: out[co][voxel] += W[co][ci] * in[ci][voxel
+// + tap] with M = output channel (two 16-blocks), N = 16 consecutive voxels
+// along x, K = the 32 input channels of one tap, one v_mfma_f32_16x16x32_bf16
+// per (tap, M-block, N-block).  Operand layout of that instruction on gfx950
+// (probed): lane l holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16],
+// i = 0..7, and receives D[4 (l / 16) + r][l % 16], r = 0..3 -- so each lane
+// ends with 4 consecutive output channels of one voxel, an 8-byte channel-last
+// store.
+//
+// A block of 4 waves owns 4 (y) x 32 (x) output voxels and marches through a
+// chunk of z planes.  The layer's weights are staged in LDS once per block
+// (27 x 32 x 32 bf16, tap-major, output channel, input channel); input planes
+// live in a ring of 3 LDS planes of 6 x 34 voxels (faces clamped), and the next
+// plane's loads are issued before the current plane's matrix products.  The
+// last layer's epilogue evaluates the head, the normalisation, FA, confidence,
+// the mask and the helix / intrusion angles.
+#include "st_device.h"
+#include "st_surrogate.h"
+
+namespace st {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int C = kSgChannels;
+constexpr int TY = 4, TX = 32, RY = TY + 2, RX = TX + 2;
+constexpr int PLANE_VOX = RY * RX;  // voxels of one staged plane
+
+__device__ __forceinline__ int64_t clampi(int64_t v, int64_t n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+// Packs the float32 blob into bf16 operand layouts: layer 1 as [co][k] (k < 27 a
+// tap, the rest 0), layers 2..5 as [tap][co][ci].
+__global__ void k_sg_pack(const float* blob, __bf16* w1, __bf16* w25) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < C * 32) {
+    const int co = static_cast<int>(i / 32), k = static_cast<int>(i % 32);
+    w1[i] = static_cast<__bf16>(k < 27 ? blob[kSgOffW1 + co * 27 + k] : 0.f);
+  }
+  const int64_t per = 27 * C * C;
+  if (i < 4 * per) {
+    const int layer = static_cast<int>(i / per);  // 0 -> network layer 2
+    const int64_t r = i % per;
+    const int tap = static_cast<int>(r / (C * C)), co = static_cast<int>((r / C) % C),
+              ci = static_cast<int>(r % C);
+    w25[i] = static_cast<__bf16>(blob[kSgOffW2 + layer * kSgLayerStride + (co * C + ci) * 27 + tap]);
+  }
+}
+
+// FIRST: input is the raw volume (one channel); LAST: the epilogue is the head.
+template <bool FIRST, bool LAST, typename Tin>
+__global__ __launch_bounds__(256) void k_sg_conv(const SgConvParams p) {
+  constexpr int WN = FIRST ? C * 32 : 27 * C * C;             // bf16 weights staged
+  constexpr int AN = FIRST ? 3 * PLANE_VOX : 3 * PLANE_VOX * C;  // bf16 activations staged
+  __shared__ __attribute__((aligned(16))) __bf16 wl[WN];
+  __shared__ __attribute__((aligned(16))) __bf16 al[AN];
+  __shared__ float hl[LAST ? 4 * TX * (C + 1) : 1];  // per wave: 32 voxels x 32 channels (+1 pad)
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t b = blockIdx.x;
+  const int64_t xt = b % p.x_tiles;
+  b /= p.x_tiles;
+  const int64_t yt = b % p.y_tiles;
+  const int64_t zc = b / p.y_tiles;
+  const int64_t x0 = xt * TX, y0 = yt * TY;
+  const int64_t nz = p.nz, ny = p.ny, nx = p.nx;
+  const int64_t z0 = zc * p.zchunk;
+  const int64_t z1 = (z0 + p.zchunk) < nz ? (z0 + p.zchunk) : nz;
+
+  // weights: 16-byte chunks
+  {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(FIRST ? p.w1 : p.w);
+    bf16x8* dst = reinterpret_cast<bf16x8*>(wl);
+    for (int i = tid; i < WN / 8; i += 256) dst[i] = src[i];
+  }
+
+  const double in_scale = FIRST ? static_cast<double>(p.scale_offset[0]) : 0.0;
+  const double in_offset = FIRST ? static_cast<double>(p.scale_offset[1]) : 0.0;
+
+  // staging of one input plane (index zi, clamped) into ring slot s
+  // FIRST: one value per voxel (normalised, bf16); else 4 chunks of 16 bytes per voxel
+  constexpr int PER = FIRST ? (PLANE_VOX + 255) / 256 : (PLANE_VOX * 4 + 255) / 256;
+  auto plane_base = [&](int64_t zi) { return clampi(zi, nz) * ny * nx; };
+  auto load_plane = [&](int64_t zi, bf16x8 (&pf)[PER], float (&pv)[PER]) {
+    const int64_t pb = plane_base(zi);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int c = tid + 256 * j;
+      if constexpr (FIRST) {
+        const int vi = c < PLANE_VOX ? c : PLANE_VOX - 1;
+        const int row = vi / RX, col = vi % RX;
+        const int64_t g = pb + clampi(y0 - 1 + row, ny) * nx + clampi(x0 - 1 + col, nx);
+        pv[j] = static_cast<float>(static_cast<const Tin*>(p.vol)[g]);
+      } else {
+        const int cc = c < PLANE_VOX * 4 ? c : PLANE_VOX * 4 - 1;
+        const int vi = cc >> 2, part = cc & 3;
+        const int row = vi / RX, col = vi % RX;
+        const int64_t g = pb + clampi(y0 - 1 + row, ny) * nx + clampi(x0 - 1 + col, nx);
+        pf[j] = reinterpret_cast<const bf16x8*>(p.in + g * C)[part];
+      }
+    }
+  };
+  auto store_plane = [&](int s, const bf16x8 (&pf)[PER], const float (&pv)[PER]) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int c = tid + 256 * j;
+      if constexpr (FIRST) {
+        if (c < PLANE_VOX)  // float64 affine map (exact product, one rounding), then float32, then bf16
+          al[s * PLANE_VOX + c] = static_cast<__bf16>(
+              static_cast<float>(fma(static_cast<double>(pv[j]), in_scale, in_offset)));
+      } else {
+        if (c < PLANE_VOX * 4) reinterpret_cast<bf16x8*>(al)[s * PLANE_VOX * 4 + c] = pf[j];
+      }
+    }
+  };
+
+  bf16x8 pf[PER];
+  float pv[PER];
+  load_plane(z0 - 1, pf, pv);
+  store_plane(0, pf, pv);
+  load_plane(z0, pf, pv);
+  store_plane(1, pf, pv);
+  load_plane(z0 + 1, pf, pv);
+  store_plane(2, pf, pv);
+  __syncthreads();
+
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t yo = y0 + wave;
+  const float* bias = p.bias;
+#pragma unroll 1
+  for (int64_t z = z0; z < z1; ++z) {
+    // ring slot of input plane z + d is (z - z0 + 1 + d) mod 3
+    const int s0 = static_cast<int>((z - z0) % 3);  // plane z - 1
+    const bool more = z + 1 < z1;
+    if (more) load_plane(z + 2, pf, pv);  // in flight during the products
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if constexpr (FIRST) {
+      // K = 32 "taps" of the single input channel (27 real, 5 zero)
+      bf16x8 bo[2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = 8 * lk + i;
+          if (k < 27) {
+            const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;  // offsets + 1
+            const int s = (s0 + dz) % 3;
+            bo[n][i] = al[s * PLANE_VOX + (wave + dy) * RX + 16 * n + li + dx];
+          } else {
+            bo[n][i] = static_cast<__bf16>(0.f);
+          }
+        }
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const bf16x8 a = reinterpret_cast<const bf16x8*>(wl)[(16 * m + li) * 4 + lk];
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bo[n], acc[m][n], 0, 0, 0);
+      }
+    } else {
+      const bf16x8* a8 = reinterpret_cast<const bf16x8*>(al);
+      const bf16x8* w8 = reinterpret_cast<const bf16x8*>(wl);
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        const int s = (s0 + dz) % 3;
+        bf16x8 bo[2], ao[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          bo[n] = a8[(s * PLANE_VOX + (wave + dy) * RX + 16 * n + li + dx) * 4 + lk];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) ao[m] = w8[(t * C + 16 * m + li) * 4 + lk];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao[m], bo[n], acc[m][n], 0, 0, 0);
+      }
+    }
+
+    if constexpr (!LAST) {
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int64_t xv = x0 + 16 * n + li;
+        if (yo < ny && xv < nx) {
+          const int64_t vox = (z * ny + yo) * nx + xv;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const int co = 16 * m + 4 * lk;
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = static_cast<__bf16>(fmaxf(acc[m][n][r] + bias[co + r], 0.f));
+            *reinterpret_cast<bf16x4*>(p.out + vox * C + co) = o;
+          }
+        }
+      }
+    } else {
+      float* h = hl + wave * TX * (C + 1);
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int co = 16 * m + 4 * lk + r;
+            h[(16 * n + li) * (C + 1) + co] = fmaxf(acc[m][n][r] + bias[co], 0.f);
+          }
+      __syncthreads();  // the head reads channels other lanes wrote
+      if (lane < TX) {
+        const int64_t xv = x0 + lane;
+        if (yo < ny && xv < nx) {
+          const int64_t vox = (z * ny + yo) * nx + xv;
+          const float* y = h + lane * (C + 1);
+          float o[5];
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            float s = p.head_b[q];
+#pragma unroll
+            for (int c = 0; c < C; ++c) s = fmaf(p.head_w[q * C + c], y[c], s);
+            o[q] = s;
+          }
+          const bool inside = p.mask == nullptr || p.mask[vox] != 0;
+          float ez = 0.f, ey = 0.f, ex = 0.f, fa = 0.f, conf = 0.f, ha = 0.f, ia = 0.f;
+          if (inside) {
+            const float nn = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+            if (nn > 0.f) {
+              const float inv = 1.f / sqrtf(nn);
+              ez = o[0] * inv; ey = o[1] * inv; ex = o[2] * inv;
+            } else {
+              ez = 1.f;
+            }
+            const float az = fabsf(ez), ay = fabsf(ey), ax = fabsf(ex);
+            const float lead = (az >= ay && az >= ax) ? ez : (ay >= ax ? ey : ex);
+            if (lead < 0.f) { ez = -ez; ey = -ey; ex = -ex; }
+            fa = 1.f / (1.f + expf(-o[3]));
+            conf = 1.f / (1.f + expf(-o[4]));
+            if (p.has_axis)
+              (void)fibre_angles(ez, ey, ex, p.center, p.dir, static_cast<double>(z),
+                                 static_cast<double>(yo), static_cast<double>(xv), ha, ia);
+          }
+          const int64_t nvox = p.n;
+          if (p.e3) { p.e3[vox] = ez; p.e3[nvox + vox] = ey; p.e3[2 * nvox + vox] = ex; }
+          if (p.fa) p.fa[vox] = fa;
+          if (p.conf) p.conf[vox] = conf;
+          if (p.ha) p.ha[vox] = ha;
+          if (p.ia) p.ia[vox] = ia;
+        }
+      }
+    }
+
+    __syncthreads();  // every read of the ring slot about to be replaced is done
+    if (more) {
+      store_plane(s0, pf, pv);  // plane z + 2 replaces plane z - 1
+      __syncthreads();
+    }
+  }
+}
+
+// Voxels inside the mask whose confidence is below the threshold take the
+// structure-tensor path's outputs.
+__global__ void k_sg_merge(const SgMergeParams p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  if (p.mask != nullptr && p.mask[i] == 0) return;
+  if (!(p.conf[i] < p.threshold)) return;
+  if (p.e3) { p.e3[i] = p.pe3[i]; p.e3[p.n + i] = p.pe3[p.n + i]; p.e3[2 * p.n + i] = p.pe3[2 * p.n + i]; }
+  if (p.fa) p.fa[i] = p.pfa[i];
+  if (p.ha) p.ha[i] = p.pha[i];
+  if (p.ia) p.ia[i] = p.pia[i];
+}
+
+template <bool FIRST, bool LAST>
+hipError_t launch_conv(const SgConvParams& p, int dtype, hipStream_t stream) {
+  const int64_t blocks = p.x_tiles * p.y_tiles * ((p.nz + p.zchunk - 1) / p.zchunk);
+  if (dtype == ST_DTYPE_U16)
+    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, uint16_t>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       stream, p);
+  else
+    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, float>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sg_pack(const float* blob, __bf16* w1, __bf16* w25, hipStream_t stream) {
+  const int64_t n = 4 * 27 * C * C;
+  hipLaunchKernelGGL(k_sg_pack, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, blob, w1, w25);
+  return hipGetLastError();
+}
+
+hipError_t launch_sg_conv(int layer, int dtype, const SgConvParams& p, hipStream_t stream) {
+  if (layer == 1) return launch_conv<true, false>(p, dtype, stream);
+  if (layer == kSgLayers) return launch_conv<false, true>(p, ST_DTYPE_F32, stream);
+  return launch_conv<false, false>(p, ST_DTYPE_F32, stream);
+}
+
+hipError_t launch_sg_merge(const SgMergeParams& p, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sg_merge, dim3(static_cast<unsigned>((p.n + 255) / 256)), dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace st

@@ -187,6 +187,33 @@ int check_device_buffer(const void* p, size_t bytes, const char* name) {
   return check_buffer(p, bytes, name);
 }
 
+int check_sizes(int64_t nz, int64_t ny, int64_t nx, int64_t* n) {
+  if (!checked_count(nz, ny, nx, n))
+    return fail(ST_ERR_INVALID_ARG, "sizes (%lld, %lld, %lld) must be >= 1, < 2^31 each, and their byte counts must fit",
+                (long long)nz, (long long)ny, (long long)nx);
+  return ST_OK;
+}
+
+int check_scales(double sigma, double rho, double truncate) {
+  if (!finite_pos(sigma) || !finite_pos(rho) || !finite_pos(truncate))
+    return fail(ST_ERR_INVALID_ARG, "sigma, rho and truncate must be finite and > 0");
+  const int rs = radius_of(sigma, truncate), rr = radius_of(rho, truncate);
+  if (rs < 1 || rr < 1)
+    return fail(ST_ERR_INVALID_ARG, "kernel radius floor(truncate*scale + 0.5) must be >= 1 (got %d, %d)", rs, rr);
+  if (rs > ST_MAX_RADIUS_SIGMA || rr > ST_MAX_RADIUS_RHO)
+    return fail(ST_ERR_UNSUPPORTED, "kernel radius %d (sigma) / %d (rho) exceeds %d / %d", rs, rr,
+                ST_MAX_RADIUS_SIGMA, ST_MAX_RADIUS_RHO);
+  return ST_OK;
+}
+
+int check_axis_args(const double* center, const double* direction, double unit[3]) {
+  return check_axis(center, direction, unit);
+}
+
+hipError_t timed_call(const char* name, hipStream_t stream, const std::function<hipError_t()>& fn) {
+  return ::timed(name, stream, fn);
+}
+
 size_t path_workspace_bytes(int64_t n) {
   if (n < 1) return 0;
   return 12 * plane_bytes(n);
@@ -495,12 +522,6 @@ int st_angles(const float* e3, const uint8_t* mask, int64_t nz, int64_t ny, int6
   hipError_t e = timed("angles", stream, [&] { return st::launch_angles(p, stream); });
   if (e != hipSuccess) return device_fail(e, "angles");
   return ST_OK;
-}
-
-int st_surrogate_infer(const void*, int, const uint8_t*, int64_t, int64_t, int64_t, const void*,
-                       size_t, double, double, double, double, const double*, const double*,
-                       float*, float*, float*, float*, float*, void*) {
-  return fail(ST_ERR_UNSUPPORTED, "the learned surrogate is not part of this build");
 }
 
 int st_profile_enable(int on) {

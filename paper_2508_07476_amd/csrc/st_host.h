@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "st_internal.h"
 
 namespace st {
@@ -41,6 +43,17 @@ struct LaunchShape {
   int64_t grad_min_blocks = 4096;
   int64_t strided_min_waves = 16384;
 };
+
+// Sizes each in [1, 2^31) with every byte count of the path fitting: *n is the
+// voxel count.  Sets the error message on failure.
+int check_sizes(int64_t nz, int64_t ny, int64_t nx, int64_t* n);
+// sigma, rho, truncate finite and positive, with radii in [1, ST_MAX_RADIUS_*].
+int check_scales(double sigma, double rho, double truncate);
+// Axis given as both pointers or neither, finite, non-zero direction; the unit
+// direction goes to unit[] (untouched without an axis).
+int check_axis_args(const double* center, const double* direction, double unit[3]);
+// Runs fn() bracketed by the library's timing events (when profiling is on).
+hipError_t timed_call(const char* name, hipStream_t stream, const std::function<hipError_t()>& fn);
 
 // Host-only validation of one volume's arguments (no HIP call); fills `a`.
 // Returns ST_OK or an error code with the message set.

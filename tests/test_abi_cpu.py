@@ -102,10 +102,48 @@ def test_angles_rejects_invalid_arguments_on_host(lib):
     assert "no output" in lib.st_last_error().decode()
 
 
-def test_surrogate_is_reported_unsupported(lib):
-    with pytest.raises(st.StError) as e:
-        st.st_surrogate_infer()
-    assert e.value.code == B.ST_ERR_UNSUPPORTED
+def _surrogate(lib, **kw):
+    a = dict(volume=FAKE, dtype=B.ST_DTYPE_U16, mask=None, nz=8, ny=8, nx=8, weights=FAKE,
+             wbytes=4 * B.ST_SURROGATE_WEIGHTS, minc=0.0, sigma=1.0, rho=2.0, truncate=4.0, center=None,
+             direction=None, e3=FAKE, fa=None, ha=None, ia=None, conf=None)
+    a.update(kw)
+    vec = lambda v: None if v is None else (ctypes.c_double * 3)(*v)  # noqa: E731
+    code = lib.st_surrogate_infer(a["volume"], a["dtype"], a["mask"], a["nz"], a["ny"], a["nx"], a["weights"],
+                                  a["wbytes"], a["minc"], a["sigma"], a["rho"], a["truncate"], vec(a["center"]),
+                                  vec(a["direction"]), a["e3"], a["fa"], a["ha"], a["ia"], a["conf"], None)
+    return code, lib.st_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code,text", [
+    (dict(volume=None), B.ST_ERR_INVALID_ARG, "volume is NULL"),
+    (dict(dtype=3), B.ST_ERR_INVALID_ARG, "dtype"),
+    (dict(nz=0), B.ST_ERR_INVALID_ARG, "sizes"),
+    (dict(weights=None), B.ST_ERR_INVALID_ARG, "weights is NULL"),
+    (dict(wbytes=100), B.ST_ERR_INVALID_ARG, "weights_bytes"),
+    (dict(minc=1.5), B.ST_ERR_INVALID_ARG, "min_confidence"),
+    (dict(minc=float("nan")), B.ST_ERR_INVALID_ARG, "min_confidence"),
+    (dict(minc=0.5, sigma=0.0), B.ST_ERR_INVALID_ARG, "sigma"),
+    (dict(minc=0.5, rho=9.0), B.ST_ERR_UNSUPPORTED, "exceeds"),
+    (dict(center=(1, 2, 3)), B.ST_ERR_INVALID_ARG, "both"),
+    (dict(ha=FAKE), B.ST_ERR_INVALID_ARG, "need an axis"),
+    (dict(e3=None), B.ST_ERR_INVALID_ARG, "no output"),
+])
+def test_surrogate_rejects_invalid_arguments_on_host(lib, kw, code, text):
+    got, msg = _surrogate(lib, **kw)
+    assert got == code, msg
+    assert text in msg
+
+
+def test_surrogate_scales_are_not_needed_without_fallback(lib):
+    # min_confidence 0: sigma/rho are unused, so an invalid value passes host
+    # validation and the call fails later, at the device-buffer check
+    got, msg = _surrogate(lib, minc=0.0, sigma=0.0)
+    assert "sigma" not in msg
+
+
+def test_surrogate_weight_count_matches_oracle(lib):
+    from oracle import surrogate
+    assert B.ST_SURROGATE_WEIGHTS == surrogate.n_weights()
 
 
 def test_error_message_is_per_call(lib):
