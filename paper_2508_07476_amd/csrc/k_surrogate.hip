@@ -12,10 +12,10 @@
 // ends with 4 consecutive output channels of one voxel, an 8-byte channel-last
 // store.
 //
-// A block of 4 waves owns 4 (y) x 32 (x) output voxels and marches through a
+// A block of 8 waves owns 8 (y) x 32 (x) output voxels and marches through a
 // chunk of z planes.  The layer's weights are staged in LDS once per block
 // (27 x 32 x 32 bf16, tap-major, output channel, input channel); input planes
-// live in a ring of 3 LDS planes of 6 x 34 voxels (faces clamped), and the next
+// live in a ring of 3 LDS planes of 10 x 34 voxels (faces clamped), and the next
 // plane's loads are issued before the current plane's matrix products.  The
 // last layer's epilogue evaluates the head, the normalisation, FA, confidence,
 // the mask and the helix / intrusion angles.
@@ -30,7 +30,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int C = kSgChannels;
-constexpr int TY = 4, TX = 32, RY = TY + 2, RX = TX + 2;
+constexpr int TY = 8, TX = 32, RY = TY + 2, RX = TX + 2;
+constexpr int NT = 64 * TY;         // threads per block: one wave per output row
 constexpr int PLANE_VOX = RY * RX;  // voxels of one staged plane
 
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
@@ -55,12 +56,12 @@ __global__ void k_sg_pack(const float* blob, __bf16* w1, __bf16* w25) {
 
 // FIRST: input is the raw volume (one channel); LAST: the epilogue is the head.
 template <bool FIRST, bool LAST, typename Tin>
-__global__ __launch_bounds__(256) void k_sg_conv(const SgConvParams p) {
+__global__ __launch_bounds__(NT) void k_sg_conv(const SgConvParams p) {
   constexpr int WN = FIRST ? C * 32 : 27 * C * C;             // bf16 weights staged
   constexpr int AN = FIRST ? 3 * PLANE_VOX : 3 * PLANE_VOX * C;  // bf16 activations staged
   __shared__ __attribute__((aligned(16))) __bf16 wl[WN];
   __shared__ __attribute__((aligned(16))) __bf16 al[AN];
-  __shared__ float hl[LAST ? 4 * TX * (C + 1) : 1];  // per wave: 32 voxels x 32 channels (+1 pad)
+  __shared__ float hl[LAST ? TY * TX * (C + 1) : 1];  // per wave: 32 voxels x 32 channels (+1 pad)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t b = blockIdx.x;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_sg_conv(const SgConvParams p) {
   {
     const bf16x8* src = reinterpret_cast<const bf16x8*>(FIRST ? p.w1 : p.w);
     bf16x8* dst = reinterpret_cast<bf16x8*>(wl);
-    for (int i = tid; i < WN / 8; i += 256) dst[i] = src[i];
+    for (int i = tid; i < WN / 8; i += NT) dst[i] = src[i];
   }
 
   const double in_scale = FIRST ? static_cast<double>(p.scale_offset[0]) : 0.0;
@@ -85,13 +86,13 @@ __global__ __launch_bounds__(256) void k_sg_conv(const SgConvParams p) {
 
   // staging of one input plane (index zi, clamped) into ring slot s
   // FIRST: one value per voxel (normalised, bf16); else 4 chunks of 16 bytes per voxel
-  constexpr int PER = FIRST ? (PLANE_VOX + 255) / 256 : (PLANE_VOX * 4 + 255) / 256;
+  constexpr int PER = FIRST ? (PLANE_VOX + NT - 1) / NT : (PLANE_VOX * 4 + NT - 1) / NT;
   auto plane_base = [&](int64_t zi) { return clampi(zi, nz) * ny * nx; };
   auto load_plane = [&](int64_t zi, bf16x8 (&pf)[PER], float (&pv)[PER]) {
     const int64_t pb = plane_base(zi);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int c = tid + 256 * j;
+      const int c = tid + NT * j;
       if constexpr (FIRST) {
         const int vi = c < PLANE_VOX ? c : PLANE_VOX - 1;
         const int row = vi / RX, col = vi % RX;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_sg_conv(const SgConvParams p) {
   auto store_plane = [&](int s, const bf16x8 (&pf)[PER], const float (&pv)[PER]) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int c = tid + 256 * j;
+      const int c = tid + NT * j;
       if constexpr (FIRST) {
         if (c < PLANE_VOX)  // float64 affine map (exact product, one rounding), then float32, then bf16
           al[s * PLANE_VOX + c] = static_cast<__bf16>(
@@ -223,8 +224,8 @@ __global__ __launch_bounds__(256) void k_sg_conv(const SgConvParams p) {
           const int64_t vox = (z * ny + yo) * nx + xv;
           const float* y = h + lane * (C + 1);
           float o[5];
-#pragma unroll
-          for (int q = 0; q < 5; ++q) {
+#pragma unroll 1
+          for (int q = 0; q < 5; ++q) {  // rolled: the head weights stream from the scalar cache
             float s = p.head_b[q];
 #pragma unroll
             for (int c = 0; c < C; ++c) s = fmaf(p.head_w[q * C + c], y[c], s);
@@ -284,10 +285,10 @@ template <bool FIRST, bool LAST>
 hipError_t launch_conv(const SgConvParams& p, int dtype, hipStream_t stream) {
   const int64_t blocks = p.x_tiles * p.y_tiles * ((p.nz + p.zchunk - 1) / p.zchunk);
   if (dtype == ST_DTYPE_U16)
-    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, uint16_t>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, uint16_t>), dim3(static_cast<unsigned>(blocks)), dim3(NT), 0,
                        stream, p);
   else
-    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, float>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, float>), dim3(static_cast<unsigned>(blocks)), dim3(NT), 0,
                        stream, p);
   return hipGetLastError();
 }

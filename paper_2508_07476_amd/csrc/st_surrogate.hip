@@ -115,7 +115,7 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
     p.e3 = e3; p.fa = fa; p.ha = ha; p.ia = ia; p.conf = conf;
     p.n = n; p.nz = nz; p.ny = ny; p.nx = nx;
     p.x_tiles = (nx + 31) / 32;
-    p.y_tiles = (ny + 3) / 4;
+    p.y_tiles = (ny + 7) / 8;  // 8 output rows per block
     p.zchunk = 16;
     p.has_axis = has_axis;
     if (has_axis)

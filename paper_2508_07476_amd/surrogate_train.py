@@ -6,7 +6,9 @@ convolutions with 32 channels, ReLU and clamped faces, then a 1x1x1 head with
 five outputs (fibre vector, FA logit, confidence logit).  Training uses
 PyTorch autograd in float32 on synthetic rod-lattice phantoms whose helix range,
 rod period and noise are drawn per volume (helix angles of +-[30, 80] degrees
-across the wall, period 3..8 voxels, noise 0.01..0.2).  Labels are the outputs
+across the wall, period 3..8 voxels, noise 0.01..0.2); half the volumes hold a
+whole, strongly curved annulus, half a piece of a wide wall (radii 60..290)
+whose axis lies outside the volume.  Labels are the outputs
 of the structure-tensor path, st_compute (sigma, rho as given), on the same
 volumes:
 
@@ -68,11 +70,19 @@ def make_pool(torch, st, helix, n, shape, sigma, rho, seed, dev):
         a_out = -float(rng.uniform(30, 80))
         if rng.random() < 0.5:
             a_in, a_out = a_out, a_in
-        r_out = min(shape[1], shape[2]) / 2 - 2
-        r_in = float(rng.uniform(0.15, 0.4)) * r_out
+        centre = None
+        if i % 2 == 0:  # a whole, strongly curved annulus inside the volume
+            r_out = min(shape[1], shape[2]) / 2 - 2
+            r_in = float(rng.uniform(0.15, 0.4)) * r_out
+        else:  # a piece of a wide, weakly curved wall: the axis lies outside the volume
+            r_in = float(rng.uniform(60.0, 160.0))
+            r_out = r_in + float(rng.uniform(60.0, 130.0))
+            r_mid, th = 0.5 * (r_in + r_out), float(rng.uniform(0, 2 * np.pi))
+            c = [(n - 1) / 2.0 for n in shape]
+            centre = (c[0], c[1] - r_mid * np.sin(th), c[2] - r_mid * np.cos(th))
         spec = helix.PhantomSpec(shape=shape, annuli=(helix.Annulus(r_in, r_out, a_in, a_out),),
                                  period=float(rng.uniform(3.0, 8.0)), noise=(float(rng.uniform(0.01, 0.2)),),
-                                 dtype="u16", seed=int(rng.integers(1 << 30)), with_mask=True)
+                                 dtype="u16", seed=int(rng.integers(1 << 30)), with_mask=True, center=centre)
         ph = helix.generate(spec, device=dev)
         lab = st.st_compute(ph["volume"], sigma, rho, mask=ph["mask"], outputs=("e3", "fa", "flags"))
         good = (lab["flags"] == 0).float()  # inside the mask and not degenerate
@@ -152,7 +162,7 @@ def main(argv=None):
         if step % 250 == 0 or step == 1:
             m = w > 0
             med = float(torch.quantile(ang[m][:200000], 0.5)) if m.any() else float("nan")
-            print(f"step {step}: loss {float(loss):.4f} dir {float(l_dir):.4f} fa {float(l_fa):.5f} "
+            print(f"step {step}: loss {float(loss.detach()):.4f} dir {float(l_dir):.4f} fa {float(l_fa):.5f} "
                   f"conf {float(l_conf):.4f} median angle {math.degrees(med):.2f} deg "
                   f"({time.time() - t0:.0f} s)", flush=True)
     blob = export_blob(model)
