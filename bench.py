@@ -92,7 +92,7 @@ def cpu_baseline(vol_u16, mask_u8, center, direction):
     import psutil
 
     import oracle
-    s = 160
+    s = 208
     z0, y0, x0 = 176, 96, 176
     crop = vol_u16[z0:z0 + s, y0:y0 + s, x0:x0 + s].cpu().numpy()
     mcrop = mask_u8[z0:z0 + s, y0:y0 + s, x0:x0 + s].cpu().numpy()
