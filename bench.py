@@ -111,6 +111,52 @@ def cpu_baseline(vol_u16, mask_u8, center, direction):
                       f"(tensor, eigen, FA, HA, IA) in FP64 NumPy, {nvox} voxels in {wall:.1f} s"}
 
 
+def run_large(args, torch, st, helix, dev):
+    """2048 x 1024 x 1024 uint16 two-annuli volume (2^31 voxels), sigma 2, rho 6,
+    outputs e3, FA, HA, IA, flags; inputs, outputs and workspace resident."""
+    shape = (2048, 1024, 1024)
+    spec = helix.spec_two_annuli_u16(shape=shape)
+    ph = helix.generate(spec, device=dev)
+    vol = ph["volume"]
+    nvox = vol.numel()
+    outs = ("e3", "fa", "ha", "ia", "flags")
+    out = {k: torch.empty(((3,) if k == "e3" else ()) + shape, dtype=torch.uint8 if k == "flags" else torch.float32,
+                          device=dev) for k in outs}
+    ws = torch.empty(st.st_workspace_bytes(shape), dtype=torch.uint8, device=dev)
+
+    def step():
+        st.st_compute(vol, 2.0, 6.0, TRUNCATE, axis_center=ph["center"], axis_direction=ph["direction"],
+                      outputs=outs, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    st.profile_reset()
+    st.profile_enable(True)
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        step()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    st.profile_enable(False)
+    kern = {k: {"avg_ms": round(v[0] / v[1], 3), "launches_per_step": v[1] / args.steps}
+            for k, v in st.profile_read().items()}
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    line = {
+        "metric": METRIC, "value": round(nvox / ms / 1e6, 4), "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2048x1024x1024 uint16 two-annuli helical phantom (noise 0.02/0.1/0.2 by "
+                               "z-thirds), sigma=2, rho=6, truncate=4; outputs e3, FA, HA, IA, flags",
+                   "shape": list(shape), "arithmetic": "f64", "intermediate_storage": "f32"},
+        "kernels": kern,
+    }
+    print(json.dumps(line), flush=True)
+
+
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2508_07476_amd", "surrogate_weights.npy")
 
 
@@ -259,6 +305,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--large", action="store_true",
+                    help="time the 2048x1024x1024 uint16 two-annuli volume (sigma 2, rho 6)")
     ap.add_argument("--surrogate", action="store_true",
                     help="time the learned surrogate (bf16 3-D CNN) on the headline volume and "
                          "report its fibre-angle error against the structure-tensor path")
@@ -294,6 +342,8 @@ def main():
         return run_batch(args, torch, st, helix, dev)
     if args.surrogate:
         return run_surrogate(args, torch, st, helix, dev)
+    if args.large:
+        return run_large(args, torch, st, helix, dev)
     spec = helix.spec_headline_u16(shape=SHAPE)
     ph = helix.generate(spec, device=dev)
     vol, mask = ph["volume"], ph["mask"]
