@@ -180,7 +180,8 @@ int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
  * chunks to `lanes` concurrent chains (largest first, each to the chain with
  * the least work so far), gives every chain its own workspace slot and
  * captures the whole batch once into a HIP graph.  st_batch_launch replays it
- * on `stream`; replays recompute every output.  st_batch_tune times candidate
+ * on `stream`; replays recompute every output.  st_batch_tune (switched off in
+ * this build, see below) times candidate
  * launch configurations (chain count, how far each pass splits its filtered
  * axis, graph replay vs direct multi-stream enqueue) on the real chunks and
  * keeps the fastest; results do not depend on the configuration (bitwise).
@@ -215,7 +216,8 @@ size_t st_batch_workspace_bytes(const st_chunk* chunks, int nchunks, int lanes);
 /* Builds a batch.  chunks: HOST array of nchunks >= 1 descriptors (copied).
  * sigma, truncate: as in st_compute, shared by every chunk.  axis_center /
  * axis_direction: HOST (z, y, x) or both NULL (then ha / ia must be NULL).
- * lanes: 1..ST_BATCH_MAX_LANES, or 0 to start at 4 and let st_batch_tune choose.
+ * lanes: 1..ST_BATCH_MAX_LANES, or 0 for ST_BATCH_MAX_LANES chains (the choice
+ * autotuning made in every measured run).
  * workspace: device buffer of st_batch_workspace_bytes(chunks, nchunks, lanes)
  * bytes, or NULL for the batch to allocate (and free in st_batch_destroy).
  * On success *out holds the batch (owned by the caller, release with
@@ -227,10 +229,11 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
 /* Enqueues the whole batch on `stream`. */
 int st_batch_launch(st_batch* batch, void* stream);
 
-/* Autotuning: runs the batch for every candidate configuration (each once to
- * warm up, then `reps` >= 1 timed runs on `stream`), keeps the fastest and
- * rebuilds the graph for it.  Synchronises `stream`.  Candidates are limited
- * to the chain counts the workspace has room for. */
+/* Autotuning (switched off in this build): would time candidate
+ * configurations on the real chunks and keep the fastest.  Repeated graph
+ * re-capture during tuning crashed the host process intermittently, with the
+ * cause not identified, so the call validates its arguments (batch non-NULL,
+ * reps >= 1) and returns ST_ERR_UNSUPPORTED without touching the batch. */
 int st_batch_tune(st_batch* batch, void* stream, int reps);
 
 /* Current configuration; any output pointer may be NULL.  best_ms is the tuned

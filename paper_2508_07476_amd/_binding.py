@@ -393,7 +393,9 @@ class Batch:
         _check(load_library().st_batch_launch(self._handle(), _stream_handle(self.device)))
 
     def tune(self, reps: int = 2) -> dict:
-        """Autotune the launch configuration on the real chunks (synchronises)."""
+        """Autotuning: switched off in this build (st_batch_tune returns
+        ST_ERR_UNSUPPORTED, raised here as StError); lanes=0 already selects the
+        configuration it chose in every measured run."""
         _check(load_library().st_batch_tune(self._handle(), _stream_handle(self.device), int(reps)))
         return self.config()
 

@@ -7,11 +7,9 @@
 // chain owns a workspace slot sized for the largest chunk and a stream of its
 // own, so small chunks that cannot fill the chip alone run side by side.  The
 // fork / join of the chains is recorded once into a HIP graph and replayed.
-// The autotuner times candidate configurations on the real chunks: chain
-// count, how far each pass splits its filtered axis, and graph replay against
-// direct multi-stream enqueue.  Every output is computed by the same kernels
-// with the same per-voxel summation order in every configuration, so results
-// are bitwise independent of the tuning.
+// Every output is computed by the same kernels with the same per-voxel
+// summation order in every configuration, so results are bitwise independent
+// of the chain count.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -234,7 +232,7 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   b->chunks = std::move(args);
   b->slot_bytes = slot;
   b->slots = slots;
-  b->lanes = lanes == 0 ? std::min(4, slots) : lanes;
+  b->lanes = lanes == 0 ? slots : lanes;
   hipError_t e = hipGetDevice(&b->device);
   const char* what = "hipGetDevice";
   if (e == hipSuccess) {
@@ -279,75 +277,18 @@ int st_batch_launch(st_batch* b, void* stream) {
   return launch(b, static_cast<hipStream_t>(stream));
 }
 
-int st_batch_tune(st_batch* b, void* stream_, int reps) {
+// Switched off: repeated re-capture of the batch graph on the same streams and
+// events, mixed with direct enqueues on those events, crashed the host process
+// intermittently on the target machine and the cause is not identified.  The
+// configuration it chose in every measured run (8 chains, graph replay, default
+// split targets) is what lanes = 0 gives.
+int st_batch_tune(st_batch* b, void*, int reps) {
   st::host::clear_error();
   if (b == nullptr) return fail(ST_ERR_INVALID_ARG, "batch is NULL");
   if (reps < 1) return fail(ST_ERR_INVALID_ARG, "reps must be >= 1");
-  DeviceScope dev(b->device);
-  if (dev.err != hipSuccess) return device_fail(dev.err, "hipSetDevice");
-  hipStream_t stream = static_cast<hipStream_t>(stream_);
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  hipError_t e = hipEventCreate(&t0);
-  if (e == hipSuccess) e = hipEventCreate(&t1);
-  if (e != hipSuccess) {
-    if (t0) (void)hipEventDestroy(t0);
-    return device_fail(e, "hipEventCreate");
-  }
-  struct Cfg {
-    int lanes;
-    bool graph;
-    st::host::LaunchShape shape;
-  };
-  auto time_cfg = [&](const Cfg& c, double* ms) -> int {
-    b->lanes = c.lanes;
-    b->use_graph = c.graph;
-    b->shape = c.shape;
-    int st = rebuild(b);
-    if (st != ST_OK) return st;
-    if ((st = launch(b, stream)) != ST_OK) return st;  // warm-up
-    hipError_t er = hipEventRecord(t0, stream);
-    for (int r = 0; r < reps && er == hipSuccess; ++r)
-      if ((st = launch(b, stream)) != ST_OK) return st;
-    if (er == hipSuccess) er = hipEventRecord(t1, stream);
-    if (er == hipSuccess) er = hipEventSynchronize(t1);
-    float f = 0.f;
-    if (er == hipSuccess) er = hipEventElapsedTime(&f, t0, t1);
-    if (er != hipSuccess) return device_fail(er, "autotune timing");
-    *ms = f / reps;
-    return ST_OK;
-  };
-  // coordinate descent: chain count, then the split targets, then the launch mode
-  const st::host::LaunchShape base;
-  Cfg best{std::min(4, b->slots), true, base};
-  double best_ms = INFINITY;
-  int st = ST_OK;
-  auto consider = [&](const Cfg& c) {
-    double ms = 0.0;
-    if (st != ST_OK) return;
-    st = time_cfg(c, &ms);
-    if (st == ST_OK && ms < best_ms) { best_ms = ms; best = c; }
-  };
-  for (int l : {1, 2, 4, 8})
-    if (l <= b->slots) consider(Cfg{l, true, base});
-  for (double f : {0.25, 4.0}) {
-    Cfg c = best;
-    c.shape.grad_min_blocks = static_cast<int64_t>(base.grad_min_blocks * f);
-    c.shape.strided_min_waves = static_cast<int64_t>(base.strided_min_waves * f);
-    consider(c);
-  }
-  {
-    Cfg c = best;
-    c.graph = false;
-    consider(c);
-  }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-  if (st != ST_OK) return st;
-  b->lanes = best.lanes;
-  b->use_graph = best.graph;
-  b->shape = best.shape;
-  b->best_ms = best_ms;
-  return rebuild(b);
+  return fail(ST_ERR_UNSUPPORTED,
+              "st_batch_tune is switched off in this build (an unexplained host crash during graph "
+              "re-capture); lanes = 0 selects its measured choice, 8 chains with graph replay");
 }
 
 int st_batch_config(const st_batch* b, int* lanes, int* use_graph, int64_t* grad_min_blocks,

@@ -6,7 +6,9 @@ every chunk's outputs equal, bitwise, those of st_compute on the same crop, and
 match the FP64 oracle run on the crop (each crop is its own volume, reflected at
 its faces; its origin places it in the axis' frame).  Graph replays with eager
 work in between, direct multi-stream enqueue and every autotuned configuration
-give the same bits.
+give the same bits (the tuning test is skipped while st_batch_tune is switched
+off); graph replays of an untuned batch (lanes = 0: 8 chains) are checked on
+their own.
 """
 
 import sys
@@ -93,6 +95,8 @@ def test_batch_matches_single_calls_and_oracle(phantom):
     b.close()
 
 
+@pytest.mark.skip(reason="st_batch_tune is switched off: repeated graph re-capture during tuning "
+                         "crashed the host process intermittently and the cause is not identified")
 def test_batch_replays_tuning_and_direct_enqueue_are_bitwise_stable(phantom):
     chunks = _chunks(phantom)
     b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
@@ -116,5 +120,29 @@ def test_batch_replays_tuning_and_direct_enqueue_are_bitwise_stable(phantom):
         for v in r.values():
             v.zero_()
     b.launch()
+    assert _same(_snapshot(b), ref)
+    b.close()
+
+
+def test_batch_graph_replays_are_bitwise_stable(phantom):
+    chunks = _chunks(phantom)
+    b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                 outputs=OUTS, lanes=0)
+    cfg = b.config()
+    _log("case: lanes=0 batch replays, config", cfg)
+    assert cfg["lanes"] == st.ST_BATCH_MAX_LANES and cfg["graph"]
+    b.launch()
+    ref = _snapshot(b)
+    for rep in range(3):  # replays with eager work (clearing the outputs) in between
+        for r in b.results:
+            for v in r.values():
+                v.zero_()
+        torch.cuda.synchronize()
+        b.launch()
+        assert _same(_snapshot(b), ref), rep
+    with pytest.raises(st.StError) as e:
+        b.tune(reps=1)
+    assert e.value.code == st.ST_ERR_UNSUPPORTED
+    b.launch()  # the batch is untouched by the refused call
     assert _same(_snapshot(b), ref)
     b.close()
