@@ -406,6 +406,10 @@ def main():
         a_s, g, o, t = roof_for(k, v[0], v[1])
         per_kernel[k] = {"avg_ms": round(a_s * 1e3, 4), "launches_per_step": v[1] / args.steps,
                          "alg_GBps": round(g, 1), "hbm_frac": round(g / HBM_PEAK_GBS, 4)}
+        tb = traffic_for(k, nvox)  # rocprofv3 bytes per launch, when current
+        if tb is not None:
+            per_kernel[k]["measured_GBps"] = round(tb / a_s / 1e9, 1)
+            per_kernel[k]["measured_frac"] = round(tb / a_s / 1e9 / HBM_PEAK_GBS, 4)
         if t is not None:
             per_kernel[k]["alu_frac"] = round(t / VALU_PEAK_TFLOPS, 4)
 
