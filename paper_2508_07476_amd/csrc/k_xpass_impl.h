@@ -4,9 +4,9 @@
 // Each block is one wave and owns one (z, y) row segment of kXTile = 256
 // outputs.  It stages the segment plus a halo of R samples on each side in LDS
 // (coalesced global loads, boundary reflection per lane only for tiles that
-// touch a face), then every lane computes kXVec = 4 consecutive outputs from a
-// register copy of its 2R+4 window, read from LDS with 16-byte loads, so each
-// LDS value feeds up to 4 outputs.
+// touch a face), then every lane computes kXVec = 4 consecutive outputs,
+// streaming its 2R+4 window from LDS in 16-byte pieces: each value is widened
+// to float64 once and feeds up to 4 outputs.
 #pragma once
 #include "st_device.h"
 

@@ -1,0 +1,72 @@
+"""bench.py's report assembly on a machine without a GPU: the roofline object
+and per-kernel figures built from kernel timings, and the source hash that
+decides whether the committed HBM byte counts still apply."""
+
+import json
+import math
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+NVOX = 512 ** 3
+STEPS = 4
+# (total ms over STEPS steps, launches) per kernel, in the shape the profiler reports
+KERN = {"grad_fused": (6.0, 4), "integrate_z": (5.6, 4), "integrate_y": (5.4, 4),
+        "integrate_x_eigen": (8.0, 4)}
+
+
+def test_dominant_kernel_roofline():
+    roof, per = bench.kernel_report(KERN, NVOX, STEPS, 6, 16)
+    json.dumps({"roofline": roof, "kernels": per})  # the line must serialise
+    assert roof["kernel"] == "integrate_x_eigen"
+    avg_s = 8.0 / 4 / 1e3
+    assert roof["avg_launch_ms"] == 2.0
+    ops = bench.alg_ops_per_voxel("integrate_x_eigen", 6, 16)
+    assert ops == 6 * 33 + bench.EIGEN_ANGLE_OPS
+    tflops = ops * 2 * NVOX / avg_s / 1e12
+    gbs = bench.ALG_BYTES_PER_VOXEL["integrate_x_eigen"] * NVOX / avg_s / 1e9
+    # the final pass is closer to the vector-ALU roof than to the HBM roof
+    assert roof["bound"] == "alu" and roof["unit"] == "TFLOP/s"
+    assert math.isclose(roof["achieved"], tflops, rel_tol=1e-3)
+    assert math.isclose(roof["frac"], roof["achieved"] / roof["peak"], rel_tol=1e-3)
+    assert math.isclose(roof["hbm_achieved_GBps"], gbs, rel_tol=1e-3)
+    assert set(per) == set(KERN)
+    for k, v in per.items():
+        assert v["launches_per_step"] == 1.0
+        assert math.isclose(v["avg_ms"], KERN[k][0] / KERN[k][1], rel_tol=1e-6)
+
+
+def test_hbm_bound_kernel():
+    roof, _ = bench.kernel_report({"integrate_z": (1.0, 1), "grad_z": (9.0, 1)}, NVOX, 1, 6, 16)
+    assert roof["kernel"] == "grad_z" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
+    gbs = bench.ALG_BYTES_PER_VOXEL["grad_z"] * NVOX / 9e-3 / 1e9
+    assert math.isclose(roof["achieved"], gbs, rel_tol=1e-3)
+    assert roof["peak"] == bench.HBM_PEAK_GBS
+
+
+def test_peaks():
+    assert math.isclose(bench.VALU_PEAK_TFLOPS, 78.6432, rel_tol=1e-9)
+    assert bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_strip_comments():
+    src = 'int a = 1; // one\n/* two\n lines */ char* s = "x // y /* z */";\nchar c = \'/\';'
+    assert bench.strip_comments(src) == 'int a = 1; char* s = "x // y /* z */"; char c = \'/\';'
+    # comments and layout do not move the hash; code does
+    assert bench.strip_comments("a  =\n b; // c") == bench.strip_comments("a = b;")
+    assert bench.strip_comments("a = b;") != bench.strip_comments("a = c;")
+
+
+def test_source_hash_covers_the_headline_sources():
+    for f in bench.KERNEL_SOURCES:
+        assert os.path.exists(os.path.join(ROOT, "paper_2508_07476_amd", "csrc", f)), f
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    with open(os.path.join(ROOT, "profiles", "traffic_headline.json")) as fh:
+        rec = json.load(fh)
+    assert len(rec["source_hash"]) == 16
+    assert set(rec["kernels"]) <= set(bench.ALG_BYTES_PER_VOXEL)
