@@ -70,3 +70,27 @@ def test_source_hash_covers_the_headline_sources():
         rec = json.load(fh)
     assert len(rec["source_hash"]) == 16
     assert set(rec["kernels"]) <= set(bench.ALG_BYTES_PER_VOXEL)
+
+
+def test_calls_to_bench_functions_match_their_signatures():
+    """Every call in bench.py to one of its own functions binds to that function's
+    signature (the GPU-only modes cannot run here, so a stale call would only
+    show on the GPU)."""
+    import ast
+    import inspect
+
+    with open(os.path.join(ROOT, "bench.py")) as fh:
+        tree = ast.parse(fh.read())
+    funcs = {n.name: getattr(bench, n.name) for n in tree.body if isinstance(n, ast.FunctionDef)}
+    checked = 0
+    for node in ast.walk(tree):
+        if isinstance(node, ast.Call) and isinstance(node.func, ast.Name) and node.func.id in funcs:
+            if any(isinstance(a, ast.Starred) for a in node.args) or any(k.arg is None for k in node.keywords):
+                continue
+            sig = inspect.signature(funcs[node.func.id])
+            try:
+                sig.bind(*[None] * len(node.args), **{k.arg: None for k in node.keywords})
+            except TypeError as e:
+                raise AssertionError(f"bench.py line {node.lineno}: {node.func.id}: {e}") from None
+            checked += 1
+    assert checked >= 8
