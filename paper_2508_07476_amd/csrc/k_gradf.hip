@@ -5,9 +5,11 @@
 // Filter order per input plane: y (G and D), then x (three combinations), then
 // z through per-column register windows, so that
 //   g_z = Dz (Gx Gy V),  g_y = Gz (Gx Dy V),  g_x = Gz (Dx Gy V).
-// A block of 4 waves owns a 4 (y) x 64 (x) tile of output columns and a chunk
-// of z outputs.  For every input plane (z halo of R on each side, reflected at
-// the faces) the (4 + 2R) x (64 + 2R) input tile is staged in LDS; the next
+// A block of TY waves owns a TY (y) x 64 (x) tile of output columns and a chunk
+// of z outputs (TY = 8 up to radius 6, where 8-row blocks still fit four waves
+// per SIMD without spilling, else 4).  For every input plane (z halo of R on
+// each side, reflected at the faces) the (TY + 2R) x (64 + 2R) input tile is
+// staged in LDS; the next
 // plane's loads are issued before the current plane is filtered.  Each
 // column's z window lives in registers and shifts by one plane per step.
 // Products leave with non-temporal stores.
@@ -16,13 +18,15 @@
 namespace st {
 namespace {
 
-template <int R, typename Tin>
-__global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
+template <int R, typename Tin, int TY = grad_tile_rows(R)>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4 : 1)))
+void k_grad_fused(const GradFusedParams p) {
   constexpr int W = 2 * R + 1;
-  constexpr int TX = kGradTX, TY = kGradTY;
+  constexpr int TX = kGradTX;
+  constexpr int NT = TX * TY;  // threads: one per output column of the tile
   constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
-  constexpr int NSTAGE = (RX * RY + 255) / 256;  // staged elements per thread
-  constexpr int NYPOS = (TY * RX + 255) / 256;   // y-filter positions per thread
+  constexpr int NSTAGE = (RX * RY + NT - 1) / NT;  // staged elements per thread
+  constexpr int NYPOS = (TY * RX + NT - 1) / NT;   // y-filter positions per thread
   __shared__ float raw[RY * RX];      // input plane (exact in float32)
   __shared__ double yb[2][TY * RX];   // y-filtered plane, float64
 
@@ -47,7 +51,7 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
   int off[NSTAGE];
 #pragma unroll
   for (int j = 0; j < NSTAGE; ++j) {
-    int s = tid + 256 * j;
+    int s = tid + NT * j;
     if (s >= RX * RY) s = RX * RY - 1;  // padding slots repeat the last element
     const int row = s / RX, col = s - (s / RX) * RX;
     const int gy = reflect_lane(static_cast<int>(y0) - R + row, static_cast<int>(ny));
@@ -66,14 +70,14 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
   auto filter_plane = [&](int64_t next, bool has_next, double& a, double& bq, double& c) {
 #pragma unroll
     for (int j = 0; j < NSTAGE; ++j) {
-      const int s = tid + 256 * j;
+      const int s = tid + NT * j;
       if (s < RX * RY) raw[s] = pf[j];
     }
     if (has_next) fetch(next);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NYPOS; ++q) {
-      const int s = tid + 256 * q;
+      const int s = tid + NT * q;
       if (s < TY * RX) {
         const int row = s / RX, col = s - (s / RX) * RX;
         double g = 0.0, d = 0.0;
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(256) void k_grad_fused(const GradFusedParams p) {
 template <typename Tin, int R>
 hipError_t launch_r(const GradFusedParams& p, hipStream_t stream) {
   const int64_t blocks = p.x_tiles * p.y_tiles * p.nchunks;
-  hipLaunchKernelGGL((k_grad_fused<R, Tin>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4), 0,
+  hipLaunchKernelGGL((k_grad_fused<R, Tin>), dim3(static_cast<unsigned>(blocks)), dim3(kGradTX, grad_tile_rows(R)), 0,
                      stream, p);
   return hipGetLastError();
 }

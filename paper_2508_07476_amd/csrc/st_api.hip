@@ -351,10 +351,14 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
       p.nz = nz; p.ny = ny; p.nx = nx;
       p.x_tiles = (nx + st::kGradTX - 1) / st::kGradTX;
-      p.y_tiles = (ny + st::kGradTY - 1) / st::kGradTY;
-      // split z until there are enough blocks to fill the chip, keeping chunks >= 8R
+      const int64_t rows = st::grad_tile_rows(ps);
+      p.y_tiles = (ny + rows - 1) / rows;
+      // split z until there are enough waves to fill the chip (grad_min_blocks
+      // counts blocks of four waves), keeping chunks >= 8R
+      const int64_t waves_per_block = rows;  // one wave per tile row
       int64_t nch = 1;
-      while (p.x_tiles * p.y_tiles * nch < shape.grad_min_blocks && nz / (2 * nch) >= 8 * ps) nch *= 2;
+      while (p.x_tiles * p.y_tiles * nch * waves_per_block < 4 * shape.grad_min_blocks && nz / (2 * nch) >= 8 * ps)
+        nch *= 2;
       p.chunk = (nz + nch - 1) / nch;
       p.nchunks = static_cast<int>((nz + p.chunk - 1) / p.chunk);
       p.wg = gs; p.wd = ds;

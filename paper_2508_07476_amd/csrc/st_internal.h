@@ -127,7 +127,10 @@ struct GradFusedParams {
   Taps wg;
   Taps wd;
 };
-constexpr int kGradTX = 64, kGradTY = 4;
+constexpr int kGradTX = 64;
+// Output rows per block (one wave per row): 8 where the kernel fits four waves
+// per SIMD without spilling, else 4.
+constexpr int grad_tile_rows(int R) { return R <= 6 ? 8 : 4; }
 constexpr int kGradMaxRadius = 8;  // larger sigma radii use the three separate passes
 hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream);
 
