@@ -236,8 +236,12 @@ int st_batch_launch(st_batch* batch, void* stream);
  * reps >= 1) and returns ST_ERR_UNSUPPORTED without touching the batch. */
 int st_batch_tune(st_batch* batch, void* stream, int reps);
 
-/* Current configuration; any output pointer may be NULL.  best_ms is the tuned
- * time per launch (0 before st_batch_tune). */
+/* Current configuration; any output pointer may be NULL.  lanes: chains in use;
+ * use_graph: 1 if launches replay the captured graph; grad_min_blocks: the
+ * gradient pass splits z until its launch holds at least 4 * grad_min_blocks
+ * waves (one wave per tile row); strided_min_waves: the same target for the
+ * integration passes; best_ms: the tuned time per launch (always 0 here, since
+ * st_batch_tune is switched off). */
 int st_batch_config(const st_batch* batch, int* lanes, int* use_graph, int64_t* grad_min_blocks,
                     int64_t* strided_min_waves, double* best_ms);
 
