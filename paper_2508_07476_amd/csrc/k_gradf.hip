@@ -110,7 +110,8 @@ void k_grad_fused(const GradFusedParams p) {
   };
 
   const bool active = (x0 + tx < nx) && (y0 + ty < ny);
-  const int64_t out_col = (y0 + ty) * nx + (x0 + tx);
+  const int64_t out_col = (y0 + ty) * p.opitch + (x0 + tx);
+  const int64_t out_plane = ny * p.opitch;
 
   // z windows: w*[k] holds the column's partial results of input plane
   // (current output z) - R + k; they shift by one plane per step (a rolled loop
@@ -139,7 +140,7 @@ void k_grad_fused(const GradFusedParams p) {
         gy = fma(p.wg.w[k], wb[k], gy);
         gx = fma(p.wg.w[k], wc[k], gx);
       }
-      const int64_t i = (z0 + j - 2 * R) * plane + out_col;
+      const int64_t i = (z0 + j - 2 * R) * out_plane + out_col;
       __builtin_nontemporal_store(static_cast<float>(gz * gz), p.prod[0] + i);
       __builtin_nontemporal_store(static_cast<float>(gz * gy), p.prod[1] + i);
       __builtin_nontemporal_store(static_cast<float>(gz * gx), p.prod[2] + i);

@@ -37,11 +37,12 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   const int lx = active ? lane : static_cast<int>(p.nx - 1 - x0);  // keep loads in range
 
   const Tin* in = static_cast<const Tin*>(p.job[job].in) + o * p.s_other + x0;
-  float* og = p.job[job].out_g + o * p.s_other + x0;
-  float* od = WITH_D ? p.job[job].out_d + o * p.s_other + x0 : nullptr;
+  float* og = p.job[job].out_g + o * p.so_other + x0;
+  float* od = WITH_D ? p.job[job].out_d + o * p.so_other + x0 : nullptr;
 
   const int64_t n = p.n_axis;
-  const int64_t sa = p.s_axis;
+  const int64_t sa = p.s_axis;   // input stride of the filtered axis
+  const int64_t soa = p.so_axis; // output stride
   const int64_t a0 = static_cast<int64_t>(chunk_id) * p.chunk;
   const int64_t len = (n - a0) < p.chunk ? (n - a0) : p.chunk;
   // relative sample i <-> axis index a0 - R + i (reflected into [0, n))
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
           if constexpr (WITH_D) d = fma(p.wd.w[k], u, d);
         }
         if (active) {
-          __builtin_nontemporal_store(static_cast<float>(g), og + (a0 + t) * sa + lane);
-          if constexpr (WITH_D) __builtin_nontemporal_store(static_cast<float>(d), od + (a0 + t) * sa + lane);
+          __builtin_nontemporal_store(static_cast<float>(g), og + (a0 + t) * soa + lane);
+          if constexpr (WITH_D) __builtin_nontemporal_store(static_cast<float>(d), od + (a0 + t) * soa + lane);
         }
       }
     };

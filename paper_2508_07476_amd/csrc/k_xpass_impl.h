@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
   const int64_t xt = blockIdx.x % p.x_tiles;
   const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
   const int64_t x0 = xt * kXTile;
-  const int64_t base = row * p.nx;
+  const int64_t base = row * p.pitch;  // inputs and products are workspace rows
 
   int idx[stage_slots(R)];
   stage_index<R>(idx, x0, p.nx, lane);
@@ -139,14 +139,15 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
   const int64_t xt = blockIdx.x % p.x_tiles;
   const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
   const int64_t x0 = xt * kXTile;
-  const int64_t base = row * p.nx;
+  const int64_t base = row * p.nx;  // mask and outputs
   const int64_t x = x0 + kXVec * lane;
 
   {
     int idx[stage_slots(R)];
     stage_index<R>(idx, x0, p.nx, lane);
+    const int64_t sbase = row * p.pitch;  // integrated products: workspace rows
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stage_row<R>(lds[c], p.s[c] + base, idx, lane);
+    for (int c = 0; c < 6; ++c) stage_row<R>(lds[c], p.s[c] + sbase, idx, lane);
   }
   // mask bytes of the lane's voxels, fetched now so the loads overlap the filtering
   uint32_t inside_bits = 0xFu;

@@ -214,9 +214,14 @@ hipError_t timed_call(const char* name, hipStream_t stream, const std::function<
   return ::timed(name, stream, fn);
 }
 
-size_t path_workspace_bytes(int64_t n) {
-  if (n < 1) return 0;
-  return 12 * plane_bytes(n);
+size_t path_workspace_bytes(int64_t nz, int64_t ny, int64_t nx) {
+  if (nz < 1 || ny < 1 || nx < 1) return 0;
+  int64_t m;
+  size_t b;
+  if (__builtin_mul_overflow(nz, ny, &m) || __builtin_mul_overflow(m, ws_pitch(nx), &m) ||
+      __builtin_mul_overflow(static_cast<size_t>(m), size_t(64), &b))
+    return 0;
+  return 12 * plane_bytes(m);
 }
 
 int prepare_path(PathArgs& a, const void* volume, int dtype, const uint8_t* mask, int64_t nz,
@@ -295,7 +300,9 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
   auto timed = [&](const char* name, hipStream_t s, auto&& fn) -> hipError_t {
     return profile ? ::timed(name, s, fn) : fn();
   };
-  const size_t pb = plane_bytes(n);
+  // workspace planes: rows of `pitch` elements (the volume's rows are nx long)
+  const int64_t pitch = ws_pitch(nx);
+  const size_t pb = plane_bytes(nz * ny * pitch);
   float* A[6];
   float* B[6];
   for (int c = 0; c < 6; ++c) {
@@ -309,17 +316,22 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
   make_taps(a.sigma, rs, ps, gs, &ds);
   make_taps(a.rho, rr, pr, gr, nullptr);
 
-  auto strided = [&](bool zaxis, int njobs, const st::StridedJob* jobs, int R, int in_dtype,
-                     bool with_d, const st::Taps& wg, const st::Taps* wd) {
+  // in_volume: the jobs read the caller's volume (rows of nx), else workspace
+  // planes; outputs are always workspace planes
+  auto strided = [&](bool zaxis, bool in_volume, int njobs, const st::StridedJob* jobs, int R,
+                     int in_dtype, bool with_d, const st::Taps& wg, const st::Taps* wd) {
     st::StridedParams p;
     std::memset(&p, 0, sizeof(p));
     for (int j = 0; j < njobs; ++j) p.job[j] = jobs[j];
     p.njobs = njobs;
     p.nx = nx;
+    const int64_t ip = in_volume ? nx : pitch;
     if (zaxis) {
-      p.n_axis = nz; p.s_axis = ny * nx; p.n_other = ny; p.s_other = nx;
+      p.n_axis = nz; p.s_axis = ny * ip; p.n_other = ny; p.s_other = ip;
+      p.so_axis = ny * pitch; p.so_other = pitch;
     } else {
-      p.n_axis = ny; p.s_axis = nx; p.n_other = nz; p.s_other = ny * nx;
+      p.n_axis = ny; p.s_axis = ip; p.n_other = nz; p.s_other = ny * ip;
+      p.so_axis = pitch; p.so_other = ny * pitch;
     }
     p.x_tiles = (nx + 63) / 64;
     p.o_tiles = (p.n_other + 3) / 4;
@@ -350,6 +362,7 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       p.vol = volume;
       for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
       p.nz = nz; p.ny = ny; p.nx = nx;
+      p.opitch = pitch;
       p.x_tiles = (nx + st::kGradTX - 1) / st::kGradTX;
       const int64_t rows = st::grad_tile_rows(ps);
       p.y_tiles = (ny + rows - 1) / rows;
@@ -369,16 +382,16 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
     {
       st::StridedJob j = {volume, B[0], B[1]};
       stage = "grad_z";
-      e = timed("grad_z", stream, [&] { return strided(true, 1, &j, ps, dtype, true, gs, &ds); });
+      e = timed("grad_z", stream, [&] { return strided(true, true, 1, &j, ps, dtype, true, gs, &ds); });
       if (e != hipSuccess) break;
     }
     {
       st::StridedJob j0 = {B[0], A[0], A[1]};
       stage = "grad_y";
-      e = timed("grad_y", stream, [&] { return strided(false, 1, &j0, ps, ST_DTYPE_F32, true, gs, &ds); });
+      e = timed("grad_y", stream, [&] { return strided(false, false, 1, &j0, ps, ST_DTYPE_F32, true, gs, &ds); });
       if (e != hipSuccess) break;
       st::StridedJob j1 = {B[1], A[2], nullptr};
-      e = timed("grad_y", stream, [&] { return strided(false, 1, &j1, ps, ST_DTYPE_F32, false, gs, nullptr); });
+      e = timed("grad_y", stream, [&] { return strided(false, false, 1, &j1, ps, ST_DTYPE_F32, false, gs, nullptr); });
       if (e != hipSuccess) break;
     }
     {
@@ -386,8 +399,8 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       std::memset(&p, 0, sizeof(p));
       p.gg = A[0]; p.dg = A[1]; p.gd = A[2];
       for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
-      p.nx = nx; p.nrows = nz * ny; p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
-      p.vec_ok = (nx % 4) == 0;
+      p.nx = nx; p.pitch = pitch; p.nrows = nz * ny; p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
+      p.vec_ok = 1;  // workspace rows: 16-byte aligned
       p.wg = gs; p.wd = ds;
       stage = "grad_x_outer";
       e = timed("grad_x_outer", stream, [&] { return st::launch_xgrad(ps, p, stream); });
@@ -399,11 +412,11 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       st::StridedJob j[6];
       for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{B[c], A[c], nullptr};
       stage = "integrate_z";
-      e = timed("integrate_z", stream, [&] { return strided(true, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
+      e = timed("integrate_z", stream, [&] { return strided(true, false, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
       if (e != hipSuccess) break;
       for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{A[c], B[c], nullptr};
       stage = "integrate_y";
-      e = timed("integrate_y", stream, [&] { return strided(false, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
+      e = timed("integrate_y", stream, [&] { return strided(false, false, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
       if (e != hipSuccess) break;
     }
     // x integration fused with eigen, FA, angles
@@ -412,7 +425,7 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       std::memset(&p, 0, sizeof(p));
       for (int c = 0; c < 6; ++c) p.s[c] = B[c];
       p.mask = mask; p.e3 = e3; p.evals = evals; p.fa = fa; p.ha = ha; p.ia = ia; p.flags = flags;
-      p.n = n; p.nz = nz; p.ny = ny; p.nx = nx; p.nrows = nz * ny;
+      p.n = n; p.nz = nz; p.ny = ny; p.nx = nx; p.pitch = pitch; p.nrows = nz * ny;
       p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
       bool vec = (nx % 4) == 0;
       for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
@@ -449,7 +462,7 @@ int st_filter_radius(double scale, double truncate) { return radius_of(scale, tr
 size_t st_workspace_bytes(int64_t nz, int64_t ny, int64_t nx) {
   int64_t n;
   if (!checked_count(nz, ny, nx, &n)) return 0;
-  return 12 * plane_bytes(n);
+  return st::host::path_workspace_bytes(nz, ny, nx);
 }
 
 int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, int64_t ny,
@@ -461,7 +474,8 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
   int st = st::host::prepare_path(a, volume, dtype, mask, nz, ny, nx, sigma, rho, truncate,
                                   axis_center, axis_direction, e3, evals, fa, ha, ia, flags);
   if (st != ST_OK) return st;
-  const size_t ws_need = st::host::path_workspace_bytes(a.n);
+  const size_t ws_need = st::host::path_workspace_bytes(a.nz, a.ny, a.nx);
+  if (ws_need == 0) return fail(ST_ERR_INVALID_ARG, "workspace size of the volume overflows");
   if (workspace == nullptr && workspace_bytes != 0)
     return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
   if (workspace != nullptr && workspace_bytes < ws_need)

@@ -158,7 +158,7 @@ bool slot_plan(const st_chunk* chunks, int nchunks, size_t* slot) {
     if (c.nz < 1 || c.ny < 1 || c.nx < 1 || __builtin_mul_overflow(c.nz, c.ny, &n) ||
         __builtin_mul_overflow(n, c.nx, &n))
       return false;
-    const size_t w = st::host::path_workspace_bytes(n);
+    const size_t w = st::host::path_workspace_bytes(c.nz, c.ny, c.nx);
     if (w == 0) return false;
     m = std::max(m, w);
   }

@@ -71,9 +71,16 @@ int check_device_buffer(const void* p, size_t bytes, const char* name);
 // the path reads or writes, and is aligned to its element size.
 int check_path_buffers(const PathArgs& a);
 
-// Workspace bytes of the pass sequence for n voxels (12 float planes, each
-// 256-byte aligned); 0 if n is out of range.
-size_t path_workspace_bytes(int64_t n);
+// Row pitch (elements) of the workspace planes: nx rounded up to a multiple of
+// 32 floats (128 bytes) above 32, else of 4.  Every 64-column wave access to a
+// workspace row then starts on a cache line whatever the volume's width, and
+// every row is 16-byte aligned.
+inline int64_t ws_pitch(int64_t nx) { return nx > 32 ? (nx + 31) / 32 * 32 : (nx + 3) / 4 * 4; }
+
+// Workspace bytes of the pass sequence for an nz x ny x nx volume (12 float
+// planes of nz * ny * ws_pitch(nx) elements, each 256-byte aligned); 0 if a size
+// is out of range.
+size_t path_workspace_bytes(int64_t nz, int64_t ny, int64_t nx);
 
 // Enqueues the pass sequence of `a` on `stream` with workspace `ws`.  With
 // `profile`, each launch is bracketed by the library's timing events (when

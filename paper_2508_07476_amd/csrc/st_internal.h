@@ -56,9 +56,11 @@ struct StridedParams {
   int nchunks;       // chunks along the filtered axis
   int64_t chunk;     // outputs per chunk along the filtered axis
   int64_t n_axis;    // length of the filtered axis
-  int64_t s_axis;    // element stride of the filtered axis
+  int64_t s_axis;    // element stride of the filtered axis in the inputs
   int64_t n_other;   // length of the remaining non-x axis
-  int64_t s_other;   // its element stride
+  int64_t s_other;   // its element stride in the inputs
+  int64_t so_axis;   // the same two strides in the outputs (pitched workspace rows)
+  int64_t so_other;
   int64_t nx;
   int64_t x_tiles;   // ceil(nx / 64)
   int64_t o_tiles;   // ceil(n_other / 4)
@@ -77,9 +79,10 @@ struct XGradParams {
   const float* gd;  // Gy Dz V  -> Gx gives g_z
   float* prod[6];   // zz, zy, zx, yy, yx, xx
   int64_t nx;
+  int64_t pitch;    // row pitch (elements) of the inputs and outputs (workspace rows)
   int64_t nrows;    // nz * ny
   int64_t x_tiles;  // ceil(nx / kXTile)
-  int vec_ok;       // nx % 4 == 0 and every output 16-byte aligned: float4 stores
+  int vec_ok;       // rows and outputs 16-byte aligned: float4 stores
   Taps wg;
   Taps wd;
 };
@@ -96,6 +99,7 @@ struct XFinalParams {
   uint8_t* flags;
   int64_t n;          // nz * ny * nx
   int64_t nz, ny, nx;
+  int64_t pitch;      // row pitch (elements) of s[] (workspace rows); mask and outputs use nx
   int64_t nrows;
   int64_t x_tiles;
   int vec_ok;         // nx % 4 == 0 and every output 16-byte aligned (flags 4-byte)
@@ -121,6 +125,7 @@ struct GradFusedParams {
   const void* vol;
   float* prod[6];     // zz, zy, zx, yy, yx, xx
   int64_t nz, ny, nx;
+  int64_t opitch;     // row pitch (elements) of prod[] (workspace rows); plane ny * opitch
   int64_t x_tiles, y_tiles;
   int64_t chunk;      // z outputs per block
   int nchunks;

@@ -73,7 +73,8 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
   const size_t w25b = align256(4 * 27 * static_cast<size_t>(C) * C * 2);
   const bool own_conf = fallback && confidence == nullptr;
   const size_t confb = own_conf ? align256(N * 4) : 0;
-  const size_t plainw = fallback ? st::host::path_workspace_bytes(n) : 0;
+  const size_t plainw = fallback ? st::host::path_workspace_bytes(nz, ny, nx) : 0;
+  if (fallback && plainw == 0) return fail(ST_ERR_INVALID_ARG, "workspace size of the volume overflows");
   const size_t pe3b = fallback && e3 ? align256(3 * N * 4) : 0;
   const size_t pfab = fallback && fa ? align256(N * 4) : 0;
   const size_t phab = fallback && ha ? align256(N * 4) : 0;

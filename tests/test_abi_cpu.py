@@ -43,9 +43,17 @@ def test_version_radius_and_workspace(lib):
     assert lib.st_version() >= 10000
     assert [lib.st_filter_radius(s, 4.0) for s in (1.0, 1.5, 2.0, 3.0, 4.0, 6.0)] == [4, 6, 8, 12, 16, 24]
     assert lib.st_filter_radius(0.0, 4.0) == -1 and lib.st_filter_radius(1.0, float("nan")) == -1
-    n = 5 * 7 * 9
-    plane = ((n * 4 + 255) // 256) * 256
-    assert lib.st_workspace_bytes(5, 7, 9) == 12 * plane
+    # 12 float planes of nz * ny * pitch elements, each rounded up to 256 bytes; the
+    # row pitch is nx rounded up to a multiple of 32 above 32, else of 4
+    def expected(nz, ny, nx):
+        pitch = -(-nx // 32) * 32 if nx > 32 else -(-nx // 4) * 4
+        return 12 * (-(-(nz * ny * pitch * 4) // 256) * 256)
+
+    for shape, pitch in (((5, 7, 9), 12), ((3, 4, 32), 32), ((3, 4, 33), 64), ((2, 3, 392), 416),
+                         ((1, 1, 1), 4), ((4, 4, 512), 512)):
+        assert lib.st_workspace_bytes(*shape) == expected(*shape), shape
+        assert expected(*shape) >= 12 * shape[0] * shape[1] * pitch * 4
+    assert lib.st_workspace_bytes(5, 7, 9) == 21504
     assert lib.st_workspace_bytes(0, 7, 9) == 0
     assert lib.st_workspace_bytes(2 ** 31, 1, 1) == 0          # each size < 2^31
     assert lib.st_workspace_bytes(2 ** 30, 2 ** 30, 2 ** 30) == 0  # product overflow
@@ -165,9 +173,10 @@ def _chunks(*specs):
 
 
 def test_batch_workspace_bytes(lib):
-    plane = lambda n: ((n * 4 + 255) // 256) * 256  # noqa: E731
     arr = _chunks(dict(nz=5, ny=7, nx=9), dict(nz=10, ny=3, nx=4))
-    slot = 12 * max(plane(5 * 7 * 9), plane(10 * 3 * 4))
+    # a slot holds the single-volume workspace of the largest chunk
+    slot = max(lib.st_workspace_bytes(5, 7, 9), lib.st_workspace_bytes(10, 3, 4))
+    assert slot == 21504
     assert lib.st_batch_workspace_bytes(arr, 2, 3) == 3 * slot
     assert lib.st_batch_workspace_bytes(arr, 2, 0) == B.ST_BATCH_MAX_LANES * slot
     assert lib.st_batch_workspace_bytes(arr, 2, 9) == 0
