@@ -13,40 +13,43 @@
 namespace st {
 namespace xpass_impl {
 
-// slots cover the tile and both halos, rounded up to whole 16-byte windows
-constexpr int stage_slots(int R) { return (kXTile + 2 * R + 4 + 63) / 64; }
-// LDS row length: every staging slot (64 per lane step) and the 16-byte reads
-// of the last lane's window fit.
-constexpr int lds_row(int R) {
-  return 64 * stage_slots(R) > ((kXTile + 2 * R + 4 + 3) / 4) * 4 ? 64 * stage_slots(R)
-                                                                   : ((kXTile + 2 * R + 4 + 3) / 4) * 4;
+// A row segment of TL lanes covers TL * kXVec outputs.  Its staging slots cover
+// the segment and both halos, rounded up to whole 16-byte windows.
+constexpr int stage_slots(int R, int TL = 64) { return (TL * kXVec + 2 * R + 4 + TL - 1) / TL; }
+// LDS row length of a segment: every staging slot (TL per lane step) and the
+// 16-byte reads of the last lane's window fit; a multiple of 4 floats.
+constexpr int lds_row(int R, int TL = 64) {
+  return TL * stage_slots(R, TL) > ((TL * kXVec + 2 * R + 4 + 3) / 4) * 4
+             ? TL * stage_slots(R, TL)
+             : ((TL * kXVec + 2 * R + 4 + 3) / 4) * 4;
 }
 
-// Row index of LDS slot i = lane + 64 j (global x = x0 - R + i, reflected into
-// [0, nx)).  Slots past the staged range repeat a valid index (their values
-// are never read).  Computed once per wave and shared by every component.
-template <int R>
-__device__ __forceinline__ void stage_index(int idx[stage_slots(R)], int64_t x0, int64_t nx, int lane) {
+// Row index of LDS slot i = l + TL j of a segment starting at x0 (global
+// x = x0 - R + i, reflected into [0, nx)); l is the lane within the segment.
+// Slots past the staged range repeat a valid index (their values are never
+// read).  Computed once per lane and shared by every component.
+template <int R, int TL = 64>
+__device__ __forceinline__ void stage_index(int idx[stage_slots(R, TL)], int64_t x0, int64_t nx, int l) {
   const int n = static_cast<int>(nx);
   const int g0 = static_cast<int>(x0) - R;
-  const bool interior = g0 >= 0 && g0 + 64 * stage_slots(R) <= n;  // wave-uniform
+  const bool interior = g0 >= 0 && g0 + TL * stage_slots(R, TL) <= n;  // wave-uniform
 #pragma unroll
-  for (int j = 0; j < stage_slots(R); ++j) {
-    const int g = g0 + lane + 64 * j;
+  for (int j = 0; j < stage_slots(R, TL); ++j) {
+    const int g = g0 + l + TL * j;
     idx[j] = interior ? g : reflect_lane(g, n);
   }
 }
 
 // Branch-free staging: all loads of the row segment are issued before the first
 // LDS write.
-template <int R>
-__device__ __forceinline__ void stage_row(float* lds, const float* row, const int idx[stage_slots(R)],
-                                          int lane) {
-  float v[stage_slots(R)];
+template <int R, int TL = 64>
+__device__ __forceinline__ void stage_row(float* lds, const float* row, const int idx[stage_slots(R, TL)],
+                                          int l) {
+  float v[stage_slots(R, TL)];
 #pragma unroll
-  for (int j = 0; j < stage_slots(R); ++j) v[j] = row[idx[j]];
+  for (int j = 0; j < stage_slots(R, TL); ++j) v[j] = row[idx[j]];
 #pragma unroll
-  for (int j = 0; j < stage_slots(R); ++j) lds[lane + 64 * j] = v[j];
+  for (int j = 0; j < stage_slots(R, TL); ++j) lds[l + TL * j] = v[j];
 }
 
 // out[v] = sum_k w[k] * lds[4 lane + v + k], v = 0..3, in float64.  The
@@ -129,25 +132,38 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
 // the float64 matrix-core and vector paths share issue slots, and the banded
 // form costs fewer operations on the vector path), then the per-voxel
 // eigen-decomposition, FA and angles of the lane's kXVec consecutive voxels.
-// Results are parked in the staged rows (free once every window has been read)
-// and leave as 16-byte stores.
-template <int R>
-__global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
-  constexpr int LR = lds_row(R);
-  __shared__ __attribute__((aligned(16))) float lds[6][LR];
+// A wave holds 64 / TL row segments of TL lanes (TL * kXVec outputs each): one
+// segment of 256 outputs, or four of 64 for rows whose width would leave much
+// of a 256-wide segment idle.  Results are parked in the staged rows (free once
+// every window has been read) and leave as 16-byte stores.
+template <int R, int TL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TL == 16 ? 4 : 1)))
+void k_xfinal(const XFinalParams p) {
+  constexpr int LR = lds_row(R, TL);
+  constexpr int RPW = 64 / TL;  // rows per wave
+  __shared__ __attribute__((aligned(16))) float lds[6][RPW * LR];
   const int lane = threadIdx.x;
+  // row segment of the lane and lane within it (0 and lane for one segment per
+  // wave, which keeps the row wave-uniform)
+  const int sub = TL == 64 ? 0 : lane / TL, l = TL == 64 ? lane : lane % TL;
   const int64_t xt = blockIdx.x % p.x_tiles;
-  const int64_t row = blockIdx.x / p.x_tiles;  // one wave per (row, x tile)
-  const int64_t x0 = xt * kXTile;
-  const int64_t base = row * p.nx;  // mask and outputs
-  const int64_t x = x0 + kXVec * lane;
+  const int64_t row0 = (blockIdx.x / p.x_tiles) * RPW;  // first row of the wave
+  const int64_t row = row0 + sub;
+  const bool row_ok = row < p.nrows;
+  const int64_t rr = row_ok ? row : p.nrows - 1;  // loads of a missing row stay in range
+  const int64_t x0 = xt * (TL * kXVec);
+  const int64_t base = rr * p.nx;  // mask and outputs
+  const int64_t x = x0 + kXVec * l;
+  float* seg[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) seg[c] = &lds[c][sub * LR];
 
   {
-    int idx[stage_slots(R)];
-    stage_index<R>(idx, x0, p.nx, lane);
-    const int64_t sbase = row * p.pitch;  // integrated products: workspace rows
+    int idx[stage_slots(R, TL)];
+    stage_index<R, TL>(idx, x0, p.nx, l);
+    const int64_t sbase = rr * p.pitch;  // integrated products: workspace rows
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stage_row<R>(lds[c], p.s[c] + sbase, idx, lane);
+    for (int c = 0; c < 6; ++c) stage_row<R, TL>(seg[c], p.s[c] + sbase, idx, l);
   }
   // mask bytes of the lane's voxels, fetched now so the loads overlap the filtering
   uint32_t inside_bits = 0xFu;
@@ -163,11 +179,21 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
 
   double acc[6][kXVec];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) conv4<R>(lds[c], lane, p.w, acc[c]);
+  for (int c = 0; c < 6; ++c) conv4<R>(seg[c], l, p.w, acc[c]);
   __syncthreads();  // every window read before the rows receive results
 
-  const double pz = static_cast<double>(row / p.ny);
-  const double py = static_cast<double>(row % p.ny);
+  // (z, y) of the lane's row; with several rows per wave the wave's first row
+  // is divided once and stepped (at most 64 / TL - 1 steps)
+  double pz, py;
+  if constexpr (TL == 64) {
+    pz = static_cast<double>(row / p.ny);
+    py = static_cast<double>(row % p.ny);
+  } else {
+    int64_t pzi = row0 / p.ny, pyi = row0 % p.ny + sub;
+    while (pyi >= p.ny) { pyi -= p.ny; ++pzi; }
+    pz = static_cast<double>(pzi);
+    py = static_cast<double>(pyi);
+  }
   const int64_t n = p.n;
 #pragma unroll 1
   for (int v = 0; v < kXVec; ++v) {
@@ -198,19 +224,19 @@ __global__ __launch_bounds__(64) void k_xfinal(const XFinalParams p) {
         fl |= ST_FLAG_ON_AXIS;
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) lds[q][kXVec * lane + v] = res[q];
-    if (xv < p.nx) {  // optional outputs: scalar stores
+    for (int q = 0; q < 6; ++q) seg[q][kXVec * l + v] = res[q];
+    if (row_ok && xv < p.nx) {  // optional outputs: scalar stores
       const int64_t i = base + xv;
       if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
       if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
-  if (x >= p.nx) return;
+  if (!row_ok || x >= p.nx) return;
   // the lane reads back only what it wrote: no barrier needed
   float o4[6][kXVec];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    const float4 t = *reinterpret_cast<const float4*>(&lds[q][kXVec * lane]);
+    const float4 t = *reinterpret_cast<const float4*>(&seg[q][kXVec * l]);
     o4[q][0] = t.x; o4[q][1] = t.y; o4[q][2] = t.z; o4[q][3] = t.w;
   }
   const bool vec_ok = p.vec_ok != 0;
@@ -231,11 +257,23 @@ hipError_t launch_xgrad_r(const XGradParams& p, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// p.tile_lanes selects the segment width (64, or 16 for radii up to
+// kXNarrowMaxRadius); p.x_tiles must be ceil(nx / (tile_lanes * kXVec)).
 template <int R>
 hipError_t launch_xfinal_r(const XFinalParams& p, hipStream_t stream) {
-  const int64_t blocks = p.x_tiles * p.nrows;
-  hipLaunchKernelGGL((k_xfinal<R>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
-  return hipGetLastError();
+  if (p.tile_lanes == 64) {
+    const int64_t blocks = p.x_tiles * p.nrows;
+    hipLaunchKernelGGL((k_xfinal<R, 64>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
+    return hipGetLastError();
+  }
+  if constexpr (R <= kXNarrowMaxRadius) {
+    if (p.tile_lanes == 16) {
+      const int64_t blocks = p.x_tiles * ((p.nrows + 3) / 4);
+      hipLaunchKernelGGL((k_xfinal<R, 16>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace xpass_impl

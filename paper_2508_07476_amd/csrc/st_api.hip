@@ -426,7 +426,14 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       for (int c = 0; c < 6; ++c) p.s[c] = B[c];
       p.mask = mask; p.e3 = e3; p.evals = evals; p.fa = fa; p.ha = ha; p.ia = ia; p.flags = flags;
       p.n = n; p.nz = nz; p.ny = ny; p.nx = nx; p.pitch = pitch; p.nrows = nz * ny;
-      p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
+      // segments of 64 lanes (256 outputs), or of 16 (64 outputs, four rows per
+      // wave) where that fills at least 5 % more of the lanes
+      auto fill = [&](int64_t tl) {
+        const int64_t t = tl * st::kXVec;
+        return static_cast<double>(nx) / static_cast<double>(t * ((nx + t - 1) / t));
+      };
+      p.tile_lanes = (pr <= st::kXNarrowMaxRadius && fill(16) >= fill(64) + 0.05) ? 16 : 64;
+      p.x_tiles = (nx + p.tile_lanes * st::kXVec - 1) / (p.tile_lanes * st::kXVec);
       bool vec = (nx % 4) == 0;
       for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
                             static_cast<const void*>(fa), static_cast<const void*>(ha),

@@ -101,7 +101,8 @@ struct XFinalParams {
   int64_t nz, ny, nx;
   int64_t pitch;      // row pitch (elements) of s[] (workspace rows); mask and outputs use nx
   int64_t nrows;
-  int64_t x_tiles;
+  int64_t x_tiles;    // ceil(nx / (tile_lanes * kXVec))
+  int tile_lanes;     // lanes per row segment: 64 (one row per wave) or 16 (four)
   int vec_ok;         // nx % 4 == 0 and every output 16-byte aligned (flags 4-byte)
   int has_axis;
   double center[3];   // (z, y, x)
@@ -110,7 +111,8 @@ struct XFinalParams {
 };
 
 constexpr int kXVec = 4;                 // consecutive x outputs per lane
-constexpr int kXTile = 64 * kXVec;       // x outputs per wave
+constexpr int kXTile = 64 * kXVec;       // x outputs per wave (one row segment of 64 lanes)
+constexpr int kXNarrowMaxRadius = 16;    // radii with 16-lane segments of the final pass
 constexpr int kRowsPerBlock = 4;         // rows per block of the angle kernel (one per wave)
 
 hipError_t launch_xgrad(int R, const XGradParams& p, hipStream_t stream);
