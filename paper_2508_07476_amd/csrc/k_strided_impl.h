@@ -17,7 +17,10 @@
 namespace st {
 namespace strided_impl {
 
-template <int R, typename Tin, bool WITH_D>
+// SAME: the outputs have the inputs' strides (every pass but the gradient's
+// z pass over the caller's volume); one stride pair then serves both, which
+// keeps the scalar registers within budget.
+template <int R, typename Tin, bool WITH_D, bool SAME>
 __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;  // 0..63, x within the tile
@@ -37,12 +40,13 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   const int lx = active ? lane : static_cast<int>(p.nx - 1 - x0);  // keep loads in range
 
   const Tin* in = static_cast<const Tin*>(p.job[job].in) + o * p.s_other + x0;
-  float* og = p.job[job].out_g + o * p.so_other + x0;
-  float* od = WITH_D ? p.job[job].out_d + o * p.so_other + x0 : nullptr;
+  const int64_t so = SAME ? p.s_other : p.so_other;
+  float* og = p.job[job].out_g + o * so + x0;
+  float* od = WITH_D ? p.job[job].out_d + o * so + x0 : nullptr;
 
   const int64_t n = p.n_axis;
-  const int64_t sa = p.s_axis;   // input stride of the filtered axis
-  const int64_t soa = p.so_axis; // output stride
+  const int64_t sa = p.s_axis;                     // input stride of the filtered axis
+  const int64_t soa = SAME ? sa : p.so_axis;       // output stride
   const int64_t a0 = static_cast<int64_t>(chunk_id) * p.chunk;
   const int64_t len = (n - a0) < p.chunk ? (n - a0) : p.chunk;
   // relative sample i <-> axis index a0 - R + i (reflected into [0, n))
@@ -89,12 +93,22 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   }
 }
 
+// Outputs with strides of their own are supported by the two-output variant
+// only (the gradient's z pass); other variants reject them.
 template <typename Tin, bool WITH_D, int R>
 hipError_t launch_r(const StridedParams& p, hipStream_t stream) {
   const int64_t blocks = p.x_tiles * p.o_tiles * p.nchunks * p.njobs;
-  hipLaunchKernelGGL((k_strided<R, Tin, WITH_D>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4),
-                     0, stream, p);
-  return hipGetLastError();
+  if (p.so_axis == p.s_axis && p.so_other == p.s_other) {
+    hipLaunchKernelGGL((k_strided<R, Tin, WITH_D, true>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4),
+                       0, stream, p);
+    return hipGetLastError();
+  }
+  if constexpr (WITH_D) {
+    hipLaunchKernelGGL((k_strided<R, Tin, WITH_D, false>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4),
+                       0, stream, p);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace strided_impl
