@@ -239,15 +239,17 @@ void k_xfinal(const XFinalParams p) {
     const float4 t = *reinterpret_cast<const float4*>(&seg[q][kXVec * l]);
     o4[q][0] = t.x; o4[q][1] = t.y; o4[q][2] = t.z; o4[q][3] = t.w;
   }
-  const bool vec_ok = p.vec_ok != 0;
+  // float4 stores where the row segment starts on 16 bytes (x is a multiple of 4)
+  auto vec_at = [&](int64_t off) { return p.vec_ok != 0 && (off & 3) == 0; };
   if (p.e3) {
-    store4(p.e3 + base, x, p.nx, vec_ok, o4[0]);
-    store4(p.e3 + n + base, x, p.nx, vec_ok, o4[1]);
-    store4(p.e3 + 2 * n + base, x, p.nx, vec_ok, o4[2]);
+    store4(p.e3 + base, x, p.nx, vec_at(base), o4[0]);
+    store4(p.e3 + n + base, x, p.nx, vec_at(n + base), o4[1]);
+    store4(p.e3 + 2 * n + base, x, p.nx, vec_at(2 * n + base), o4[2]);
   }
-  if (p.fa) store4(p.fa + base, x, p.nx, vec_ok, o4[3]);
-  if (p.ha) store4(p.ha + base, x, p.nx, vec_ok, o4[4]);
-  if (p.ia) store4(p.ia + base, x, p.nx, vec_ok, o4[5]);
+  const bool vec_row = vec_at(base);
+  if (p.fa) store4(p.fa + base, x, p.nx, vec_row, o4[3]);
+  if (p.ha) store4(p.ha + base, x, p.nx, vec_row, o4[4]);
+  if (p.ia) store4(p.ia + base, x, p.nx, vec_row, o4[5]);
 }
 
 template <int R>

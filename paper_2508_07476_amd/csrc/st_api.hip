@@ -434,7 +434,7 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       };
       p.tile_lanes = (pr <= st::kXNarrowMaxRadius && fill(16) >= fill(64) + 0.05) ? 16 : 64;
       p.x_tiles = (nx + p.tile_lanes * st::kXVec - 1) / (p.tile_lanes * st::kXVec);
-      bool vec = (nx % 4) == 0;
+      bool vec = true;  // the kernel also checks each row's and plane's offset
       for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
                             static_cast<const void*>(fa), static_cast<const void*>(ha),
                             static_cast<const void*>(ia)})

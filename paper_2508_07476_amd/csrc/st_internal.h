@@ -103,7 +103,8 @@ struct XFinalParams {
   int64_t nrows;
   int64_t x_tiles;    // ceil(nx / (tile_lanes * kXVec))
   int tile_lanes;     // lanes per row segment: 64 (one row per wave) or 16 (four)
-  int vec_ok;         // nx % 4 == 0 and every output 16-byte aligned (flags 4-byte)
+  int vec_ok;         // every float output 16-byte aligned: float4 stores wherever
+                      // the row's element offset is a multiple of 4
   int has_axis;
   double center[3];   // (z, y, x)
   double dir[3];      // unit (z, y, x)
