@@ -12,7 +12,8 @@
 // staged in LDS; the next
 // plane's loads are issued before the current plane is filtered.  Each
 // column's z window lives in registers and shifts by one plane per step.
-// Products leave with non-temporal stores.
+// Products leave with non-temporal stores into workspace planes whose rows have
+// the workspace pitch (the input volume has rows of nx).
 #include "st_device.h"
 
 namespace st {

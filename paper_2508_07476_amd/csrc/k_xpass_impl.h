@@ -1,12 +1,15 @@
 // x-axis passes: the last gradient pass fused with the outer product, and the
 // last integration pass fused with the eigen-decomposition, FA and angles.
 //
-// Each block is one wave and owns one (z, y) row segment of kXTile = 256
-// outputs.  It stages the segment plus a halo of R samples on each side in LDS
-// (coalesced global loads, boundary reflection per lane only for tiles that
-// touch a face), then every lane computes kXVec = 4 consecutive outputs,
-// streaming its 2R+4 window from LDS in 16-byte pieces: each value is widened
-// to float64 once and feeds up to 4 outputs.
+// Each block is one wave.  It owns one (z, y) row segment of kXTile = 256
+// outputs, or (final pass, narrow rows) four segments of 64 outputs from
+// consecutive rows.  It stages each segment plus a halo of R samples on each
+// side in LDS (coalesced global loads, boundary reflection per lane only for
+// segments that touch a face), then every lane computes kXVec = 4 consecutive
+// outputs, streaming its 2R+4 window from LDS in 16-byte pieces: each value is
+// widened to float64 once and feeds up to 4 outputs.  Intermediate planes are
+// read and written with the workspace row pitch; the caller's mask and outputs
+// with rows of nx.
 #pragma once
 #include "st_device.h"
 
