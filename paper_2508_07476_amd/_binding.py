@@ -316,7 +316,8 @@ class Batch:
     tensor), ``rho``, optional ``origin`` (z, y, x) of ``volume[0, 0, 0]`` in the
     axis' coordinates (default 0) and optional ``mask``.  Outputs (``outputs``
     names) are allocated here and returned per chunk by :attr:`results`.
-    ``lanes`` 0 leaves the chain count to :meth:`tune`.
+    ``lanes`` is the number of concurrent chains (1..ST_BATCH_MAX_LANES); 0 takes
+    ST_BATCH_MAX_LANES chains with graph replay.
     """
 
     def __init__(self, chunks, sigma: float, truncate: float = 4.0, axis_center=None,
