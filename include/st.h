@@ -240,8 +240,9 @@ int st_batch_tune(st_batch* batch, void* stream, int reps);
  * use_graph: 1 if launches replay the captured graph; grad_min_blocks: the
  * gradient pass splits z until its launch holds at least 4 * grad_min_blocks
  * waves (one wave per tile row); strided_min_waves: the same target for the
- * integration passes; best_ms: the tuned time per launch (always 0 here, since
- * st_batch_tune is switched off). */
+ * integration passes (with more than one chain both are a quarter of a lone
+ * st_compute's, since the chains fill the chip together); best_ms: the tuned
+ * time per launch (always 0 here, since st_batch_tune is switched off). */
 int st_batch_config(const st_batch* batch, int* lanes, int* use_graph, int64_t* grad_min_blocks,
                     int64_t* strided_min_waves, double* best_ms);
 

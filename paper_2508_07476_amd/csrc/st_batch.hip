@@ -233,6 +233,12 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   b->slot_bytes = slot;
   b->slots = slots;
   b->lanes = lanes == 0 ? slots : lanes;
+  if (b->lanes > 1) {
+    // concurrent chains fill the chip together: split each chunk's passes a
+    // quarter as far as a lone volume would be (fewer z halo planes)
+    b->shape.grad_min_blocks /= 4;
+    b->shape.strided_min_waves /= 4;
+  }
   hipError_t e = hipGetDevice(&b->device);
   const char* what = "hipGetDevice";
   if (e == hipSuccess) {
