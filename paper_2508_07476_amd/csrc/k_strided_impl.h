@@ -44,16 +44,19 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
   float* og = p.job[job].out_g + o * so + x0;
   float* od = WITH_D ? p.job[job].out_d + o * so + x0 : nullptr;
 
-  const int64_t n = p.n_axis;
+  // axis positions fit in 32 bits (each size < 2^31), so their compares and the
+  // reflection stay on the scalar unit; only the element offsets are 64-bit
+  const int n = static_cast<int>(p.n_axis);
   const int64_t sa = p.s_axis;                     // input stride of the filtered axis
   const int64_t soa = SAME ? sa : p.so_axis;       // output stride
-  const int64_t a0 = static_cast<int64_t>(chunk_id) * p.chunk;
-  const int64_t len = (n - a0) < p.chunk ? (n - a0) : p.chunk;
+  const int a0 = chunk_id * static_cast<int>(p.chunk);
+  const int len = (n - a0) < p.chunk ? (n - a0) : static_cast<int>(p.chunk);
   // relative sample i <-> axis index a0 - R + i (reflected into [0, n))
   // streaming (non-temporal) loads and stores: every sample is read once per
   // chunk and every output once, so neither should displace cached data
-  auto sample = [&](int64_t i) {
-    return static_cast<float>(__builtin_nontemporal_load(in + reflect(a0 - R + i, n) * sa + lx));
+  auto sample = [&](int i) {
+    return static_cast<float>(
+        __builtin_nontemporal_load(in + static_cast<int64_t>(reflect_lane(a0 - R + i, n)) * sa + lx));
   };
   // window and accumulators in float64 (each sample is widened once, on entry)
 
@@ -67,9 +70,9 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
 #pragma unroll
   for (int j = 0; j < W; ++j) pre[j] = sample(2 * R + j);
 
-  for (int64_t tb = 0; tb < len; tb += W) {
+  for (int tb = 0; tb < len; tb += W) {
     auto step = [&]<int J>(std::integral_constant<int, J>) {
-      const int64_t t = tb + J;
+      const int t = tb + J;
       const double v = pre[J];
       if (t + W < len) pre[J] = sample(t + W + 2 * R);  // same step of the next block
       win[(J + 2 * R) % W] = v;
@@ -82,8 +85,9 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
           if constexpr (WITH_D) d = fma(p.wd.w[k], u, d);
         }
         if (active) {
-          __builtin_nontemporal_store(static_cast<float>(g), og + (a0 + t) * soa + lane);
-          if constexpr (WITH_D) __builtin_nontemporal_store(static_cast<float>(d), od + (a0 + t) * soa + lane);
+          const int64_t at = static_cast<int64_t>(a0 + t) * soa + lane;
+          __builtin_nontemporal_store(static_cast<float>(g), og + at);
+          if constexpr (WITH_D) __builtin_nontemporal_store(static_cast<float>(d), od + at);
         }
       }
     };
