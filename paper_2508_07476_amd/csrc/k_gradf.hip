@@ -43,8 +43,11 @@ void k_grad_fused(const GradFusedParams p) {
   const int chunk_id = static_cast<int>(b / p.y_tiles);
   const int64_t x0 = xt * TX, y0 = yt * TY;
   const int64_t nz = p.nz, ny = p.ny, nx = p.nx;
-  const int64_t z0 = static_cast<int64_t>(chunk_id) * p.chunk;
-  const int64_t len = (nz - z0) < p.chunk ? (nz - z0) : p.chunk;
+  // z positions fit in 32 bits (each size < 2^31): their compares and the
+  // reflection stay on the scalar unit; element offsets are 64-bit
+  const int nzi = static_cast<int>(nz);
+  const int z0 = chunk_id * static_cast<int>(p.chunk);
+  const int len = (nzi - z0) < p.chunk ? (nzi - z0) : static_cast<int>(p.chunk);
   const int64_t plane = ny * nx;  // < 2^31 (checked by the host)
   const Tin* vol = static_cast<const Tin*>(p.vol);
 
@@ -60,15 +63,15 @@ void k_grad_fused(const GradFusedParams p) {
     off[j] = gy * static_cast<int>(nx) + gx;
   }
   float pf[NSTAGE];
-  auto fetch = [&](int64_t zi) {  // loads of input plane zi into pf
-    const Tin* src = vol + reflect(zi, nz) * plane;
+  auto fetch = [&](int zi) {  // loads of input plane zi into pf
+    const Tin* src = vol + static_cast<int64_t>(reflect_lane(zi, nzi)) * plane;
 #pragma unroll
     for (int j = 0; j < NSTAGE; ++j) pf[j] = static_cast<float>(src[off[j]]);  // halo re-read by neighbours: keep cached
   };
 
   // Filter the staged plane (already fetched into pf) along y then x; returns the
   // three partial results of this thread's column, and prefetches plane `next`.
-  auto filter_plane = [&](int64_t next, bool has_next, double& a, double& bq, double& c) {
+  auto filter_plane = [&](int next, bool has_next, double& a, double& bq, double& c) {
 #pragma unroll
     for (int j = 0; j < NSTAGE; ++j) {
       const int s = tid + NT * j;
@@ -119,9 +122,9 @@ void k_grad_fused(const GradFusedParams p) {
   // keeps the code and the register count small).
   double wa[W], wb[W], wc[W];
   fetch(z0 - R);
-  const int64_t nplanes = len + 2 * R;
+  const int nplanes = len + 2 * R;
 #pragma unroll 1
-  for (int64_t j = 0; j < nplanes; ++j) {  // block-uniform trip count
+  for (int j = 0; j < nplanes; ++j) {  // block-uniform trip count
     double a, bq, c;
     filter_plane(z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
 #pragma unroll
@@ -141,7 +144,7 @@ void k_grad_fused(const GradFusedParams p) {
         gy = fma(p.wg.w[k], wb[k], gy);
         gx = fma(p.wg.w[k], wc[k], gx);
       }
-      const int64_t i = (z0 + j - 2 * R) * out_plane + out_col;
+      const int64_t i = static_cast<int64_t>(z0 + j - 2 * R) * out_plane + out_col;
       __builtin_nontemporal_store(static_cast<float>(gz * gz), p.prod[0] + i);
       __builtin_nontemporal_store(static_cast<float>(gz * gy), p.prod[1] + i);
       __builtin_nontemporal_store(static_cast<float>(gz * gx), p.prod[2] + i);

@@ -82,7 +82,7 @@ __device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w,
   }
 }
 
-__device__ __forceinline__ void store4(float* dst, int64_t x, int64_t nx, bool vec_ok,
+__device__ __forceinline__ void store4(float* dst, int x, int nx, bool vec_ok,
                                        const float v[kXVec]) {
   if (vec_ok && x + kXVec <= nx) {
     *reinterpret_cast<float4*>(dst + x) = make_float4(v[0], v[1], v[2], v[3]);
@@ -115,13 +115,14 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
   conv4<R>(lds[1], lane, p.wg, gy);
   conv4<R>(lds[2], lane, p.wg, gz);
 
-  const int64_t x = x0 + kXVec * lane;
-  if (x >= p.nx) return;
+  const int nxi = static_cast<int>(p.nx);  // x positions are 32-bit (nx < 2^31)
+  const int x = static_cast<int>(x0) + kXVec * lane;
+  if (x >= nxi) return;
   const bool vec_ok = p.vec_ok != 0;
   float t[kXVec];
 #define ST_PROD(idx, A, B)                                        \
   for (int v = 0; v < kXVec; ++v) t[v] = static_cast<float>(A[v] * B[v]); \
-  store4(p.prod[idx] + base, x, p.nx, vec_ok, t);
+  store4(p.prod[idx] + base, x, nxi, vec_ok, t);
   ST_PROD(0, gz, gz)
   ST_PROD(1, gz, gy)
   ST_PROD(2, gz, gx)
@@ -156,7 +157,8 @@ void k_xfinal(const XFinalParams p) {
   const int64_t rr = row_ok ? row : p.nrows - 1;  // loads of a missing row stay in range
   const int64_t x0 = xt * (TL * kXVec);
   const int64_t base = rr * p.nx;  // mask and outputs
-  const int64_t x = x0 + kXVec * l;
+  const int nxi = static_cast<int>(p.nx);  // x positions are 32-bit (nx < 2^31)
+  const int x = static_cast<int>(x0) + kXVec * l;
   float* seg[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) seg[c] = &lds[c][sub * LR];
@@ -174,7 +176,7 @@ void k_xfinal(const XFinalParams p) {
     inside_bits = 0u;
 #pragma unroll
     for (int v = 0; v < kXVec; ++v) {
-      const int64_t xr = x + v < p.nx ? x + v : p.nx - 1;
+      const int xr = x + v < nxi ? x + v : nxi - 1;
       inside_bits |= (p.mask[base + xr] != 0 ? 1u : 0u) << v;
     }
   }
@@ -200,7 +202,7 @@ void k_xfinal(const XFinalParams p) {
   const int64_t n = p.n;
 #pragma unroll 1
   for (int v = 0; v < kXVec; ++v) {
-    const int64_t xv = x + v;
+    const int xv = x + v;
     const bool inside = (inside_bits >> v) & 1u;
     double s6[6];
 #pragma unroll
@@ -228,13 +230,13 @@ void k_xfinal(const XFinalParams p) {
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) seg[q][kXVec * l + v] = res[q];
-    if (row_ok && xv < p.nx) {  // optional outputs: scalar stores
+    if (row_ok && xv < nxi) {  // optional outputs: scalar stores
       const int64_t i = base + xv;
       if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
       if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
-  if (!row_ok || x >= p.nx) return;
+  if (!row_ok || x >= nxi) return;
   // the lane reads back only what it wrote: no barrier needed
   float o4[6][kXVec];
 #pragma unroll
@@ -245,14 +247,14 @@ void k_xfinal(const XFinalParams p) {
   // float4 stores where the row segment starts on 16 bytes (x is a multiple of 4)
   auto vec_at = [&](int64_t off) { return p.vec_ok != 0 && (off & 3) == 0; };
   if (p.e3) {
-    store4(p.e3 + base, x, p.nx, vec_at(base), o4[0]);
-    store4(p.e3 + n + base, x, p.nx, vec_at(n + base), o4[1]);
-    store4(p.e3 + 2 * n + base, x, p.nx, vec_at(2 * n + base), o4[2]);
+    store4(p.e3 + base, x, nxi, vec_at(base), o4[0]);
+    store4(p.e3 + n + base, x, nxi, vec_at(n + base), o4[1]);
+    store4(p.e3 + 2 * n + base, x, nxi, vec_at(2 * n + base), o4[2]);
   }
   const bool vec_row = vec_at(base);
-  if (p.fa) store4(p.fa + base, x, p.nx, vec_row, o4[3]);
-  if (p.ha) store4(p.ha + base, x, p.nx, vec_row, o4[4]);
-  if (p.ia) store4(p.ia + base, x, p.nx, vec_row, o4[5]);
+  if (p.fa) store4(p.fa + base, x, nxi, vec_row, o4[3]);
+  if (p.ha) store4(p.ha + base, x, nxi, vec_row, o4[4]);
+  if (p.ia) store4(p.ia + base, x, nxi, vec_row, o4[5]);
 }
 
 template <int R>

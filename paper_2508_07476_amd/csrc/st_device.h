@@ -10,17 +10,9 @@
 namespace st {
 
 // Half-sample symmetric reflection of index m into [0, n): -1 -> 0, n -> n-1,
-// folded with period 2n for indices farther out.  Called with wave-uniform
-// arguments, so it runs on the scalar unit.
-__device__ __forceinline__ int64_t reflect(int64_t m, int64_t n) {
-  if (m >= 0 && m < n) return m;
-  const int64_t p = 2 * n;
-  m %= p;
-  if (m < 0) m += p;
-  return m < n ? m : p - 1 - m;
-}
-
-// Per-lane variant for small |m| excursions (x-axis halos).
+// folded with period 2n for indices farther out.  Positions are 32-bit (every
+// size is below 2^31), so with wave-uniform arguments the compares run on the
+// scalar unit, which has no 64-bit signed compare.
 __device__ __forceinline__ int reflect_lane(int m, int n) {
   if (m >= 0 && m < n) return m;
   const int p = 2 * n;
