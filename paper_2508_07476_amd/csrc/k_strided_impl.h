@@ -78,11 +78,15 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
       win[(J + 2 * R) % W] = v;
       if (t < len) {
         double g = 0.0, d = 0.0;
+        // the smoothing taps are symmetric and the derivative taps antisymmetric
+        // about the centre (bit for bit, as built): reading only taps 0..R keeps
+        // R + 1 of them in scalar registers instead of 2R + 1, which no longer
+        // fit at the largest radii
 #pragma unroll
         for (int k = 0; k < W; ++k) {
           const double u = win[(J + k) % W];
-          g = fma(p.wg.w[k], u, g);
-          if constexpr (WITH_D) d = fma(p.wd.w[k], u, d);
+          g = fma(p.wg.w[k <= R ? k : 2 * R - k], u, g);
+          if constexpr (WITH_D) d = fma(k <= R ? p.wd.w[k] : -p.wd.w[2 * R - k], u, d);
         }
         if (active) {
           const int64_t at = static_cast<int64_t>(a0 + t) * soa + lane;

@@ -59,7 +59,10 @@ __device__ __forceinline__ void stage_row(float* lds, const float* row, const in
 // window is streamed through in 16-byte pieces: each value is widened once and
 // enters the (up to) four sums it belongs to, each sum taking its taps in
 // ascending order.
-template <int R>
+// SYMMETRIC: the taps are symmetric about the centre (bit for bit, as the
+// smoothing taps are built), so only taps 0..R are read and R + 1 of them
+// occupy registers; derivative taps must use the general form.
+template <int R, bool SYMMETRIC = false>
 __device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w, double out[kXVec]) {
   constexpr int NV = (2 * R + kXVec + 3) / 4;
   const float4* src = reinterpret_cast<const float4*>(lds + 4 * lane);
@@ -76,7 +79,8 @@ __device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w,
 #pragma unroll
       for (int v = 0; v < kXVec; ++v) {
         const int k = j - v;
-        if (k >= 0 && k <= 2 * R) out[v] = fma(w.w[k], d, out[v]);
+        const int kk = SYMMETRIC && k > R ? 2 * R - k : k;
+        if (k >= 0 && k <= 2 * R) out[v] = fma(w.w[kk], d, out[v]);
       }
     }
   }
@@ -184,7 +188,7 @@ void k_xfinal(const XFinalParams p) {
 
   double acc[6][kXVec];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) conv4<R>(seg[c], l, p.w, acc[c]);
+  for (int c = 0; c < 6; ++c) conv4<R, true>(seg[c], l, p.w, acc[c]);
   __syncthreads();  // every window read before the rows receive results
 
   // (z, y) of the lane's row; with several rows per wave the wave's first row

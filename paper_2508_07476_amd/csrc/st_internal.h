@@ -64,8 +64,8 @@ struct StridedParams {
   int64_t nx;
   int64_t x_tiles;   // ceil(nx / 64)
   int64_t o_tiles;   // ceil(n_other / 4)
-  Taps wg;
-  Taps wd;
+  Taps wg;           // smoothing taps: symmetric about the centre (read as such)
+  Taps wd;           // derivative taps: antisymmetric about the centre
 };
 
 // in_dtype: ST_DTYPE_U16 or ST_DTYPE_F32.  with_d selects the two-output variant.
