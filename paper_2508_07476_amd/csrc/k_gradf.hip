@@ -28,6 +28,9 @@ void k_grad_fused(const GradFusedParams p) {
   constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
   constexpr int NSTAGE = (RX * RY + NT - 1) / NT;  // staged elements per thread
   constexpr int NYPOS = (TY * RX + NT - 1) / NT;   // y-filter positions per thread
+  // The smoothing taps are symmetric about the centre (bit for bit, as built):
+  // only taps 0..R are read, so R + 1 of them occupy scalar registers.
+  auto tg = [&](int k) { return p.wg.w[k <= R ? k : 2 * R - k]; };
   __shared__ float raw[RY * RX];      // input plane (exact in float32)
   __shared__ double yb[2][TY * RX];   // y-filtered plane, float64
 
@@ -88,7 +91,7 @@ void k_grad_fused(const GradFusedParams p) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
           const double v = raw[(row + k) * RX + col];
-          g = fma(p.wg.w[k], v, g);
+          g = fma(tg(k), v, g);
           d = fma(p.wd.w[k], v, d);
         }
         yb[0][s] = g;
@@ -101,9 +104,9 @@ void k_grad_fused(const GradFusedParams p) {
     for (int k = 0; k < W; ++k) {
       const double u = yb[0][ty * RX + tx + k];
       const double w = yb[1][ty * RX + tx + k];
-      ga = fma(p.wg.w[k], u, ga);
+      ga = fma(tg(k), u, ga);
       dc = fma(p.wd.w[k], u, dc);
-      gb = fma(p.wg.w[k], w, gb);
+      gb = fma(tg(k), w, gb);
     }
     // materialise the three results here: otherwise the compiler sinks these
     // sums towards their use in the z filter and keeps every LDS value alive
@@ -141,8 +144,8 @@ void k_grad_fused(const GradFusedParams p) {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         gz = fma(p.wd.w[k], wa[k], gz);
-        gy = fma(p.wg.w[k], wb[k], gy);
-        gx = fma(p.wg.w[k], wc[k], gx);
+        gy = fma(tg(k), wb[k], gy);
+        gx = fma(tg(k), wc[k], gx);
       }
       const int64_t i = static_cast<int64_t>(z0 + j - 2 * R) * out_plane + out_col;
       __builtin_nontemporal_store(static_cast<float>(gz * gz), p.prod[0] + i);
