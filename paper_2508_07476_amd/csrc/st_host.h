@@ -36,11 +36,12 @@ struct PathArgs {
 };
 
 // Launch shapes: how far each pass splits its filtered axis to fill the chip.
-// The gradient pass splits z until it has at least grad_min_blocks blocks; the
-// strided passes split until they have at least strided_min_waves waves (in
-// both cases only while the pieces stay long against the filter radius).  Every
-// gradient piece re-reads 2R halo planes, so the split stops at four blocks per
-// compute unit: a 512^3 volume's 1024 x-y tiles already fill the chip.
+// The gradient pass splits z until it has at least 4 * grad_min_blocks waves
+// (blocks of four waves' worth); the strided passes split until they have at
+// least strided_min_waves waves (in both cases only while the pieces stay long
+// against the filter radius).  Every gradient piece re-reads 2R halo planes, so
+// the split stops at four waves per SIMD: a 512^3 volume's x-y tiles already
+// fill the chip.  A batch of concurrent chains uses a quarter of both targets.
 struct LaunchShape {
   int64_t grad_min_blocks = 1024;
   int64_t strided_min_waves = 16384;
