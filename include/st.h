@@ -73,9 +73,12 @@ const char* st_last_error(void);
 int st_filter_radius(double scale, double truncate);
 
 /*
- * Bytes of device workspace st_compute needs for an nz*ny*nx volume
- * (12 float32 planes of nz*ny*nx values, 256-byte aligned).  Returns 0 on
- * invalid sizes (non-positive, or a byte count that overflows size_t).
+ * Bytes of device workspace st_compute needs for an nz*ny*nx volume: 12 float32
+ * planes, each 256-byte aligned, of nz*ny rows of nx values padded to a
+ * multiple of 32 (of 4 when nx <= 32), so that the intermediate planes' rows
+ * start on 128-byte lines.  The layout is internal; callers only size the
+ * buffer.  Returns 0 on invalid sizes (non-positive, or a byte count that
+ * overflows size_t).
  */
 size_t st_workspace_bytes(int64_t nz, int64_t ny, int64_t nx);
 
