@@ -212,8 +212,8 @@ typedef struct st_batch st_batch;  /* opaque */
 #define ST_BATCH_MAX_LANES 8
 
 /* Workspace bytes a batch of these chunks needs with `lanes` chains (0 = room
- * for ST_BATCH_MAX_LANES, as an autotuned batch uses); 0 if a chunk's sizes
- * are invalid. */
+ * for ST_BATCH_MAX_LANES): one slot per chain, each st_workspace_bytes of the
+ * largest chunk; 0 if a chunk's sizes are invalid. */
 size_t st_batch_workspace_bytes(const st_chunk* chunks, int nchunks, int lanes);
 
 /* Builds a batch.  chunks: HOST array of nchunks >= 1 descriptors (copied).
