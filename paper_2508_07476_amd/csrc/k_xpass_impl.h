@@ -240,6 +240,50 @@ void k_xfinal(const XFinalParams p) {
       if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
     }
   }
+  if constexpr (TL == 64) {
+    // One row per wave.  Where a destination row starts off a 16-byte boundary
+    // (nx not a multiple of 4), each lane writes the aligned group of the row
+    // that holds segment positions [4 l - k, 4 l - k + 4) (k: offset of the
+    // segment's first element inside its group) from the parked results, and
+    // lane 0 also the last k positions; groups cut by an end of the segment
+    // are written one element at a time.  Every element is written once.
+    const int64_t s0 = base + x0;
+    const bool shifted = p.vec_ok != 0 &&
+                         (((s0 & 3) != 0 && (p.fa || p.ha || p.ia)) ||
+                          (p.e3 && (((s0 & 3) | ((n + s0) & 3) | ((2 * n + s0) & 3)) != 0)));
+    if (shifted) {  // wave-uniform
+      __syncthreads();  // every lane's parked results visible
+      const int seglen = min(TL * kXVec, nxi - static_cast<int>(x0));
+      auto put = [&](float* plane, int64_t off, const float* src) {
+        float* dst = plane + off + x0;  // segment start
+        const int k = static_cast<int>((off + x0) & 3);
+        const int g = kXVec * l - k;
+        if (g >= 0 && g + kXVec <= seglen) {
+          *reinterpret_cast<float4*>(dst + g) = make_float4(src[g], src[g + 1], src[g + 2], src[g + 3]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < kXVec; ++i)
+            if (g + i >= 0 && g + i < seglen) dst[g + i] = src[g + i];
+        }
+        if (l == 0) {
+#pragma unroll
+          for (int i = 0; i < kXVec - 1; ++i) {
+            const int t = TL * kXVec - k + i;
+            if (i < k && t < seglen) dst[t] = src[t];
+          }
+        }
+      };
+      if (p.e3) {
+        put(p.e3, base, seg[0]);
+        put(p.e3, n + base, seg[1]);
+        put(p.e3, 2 * n + base, seg[2]);
+      }
+      if (p.fa) put(p.fa, base, seg[3]);
+      if (p.ha) put(p.ha, base, seg[4]);
+      if (p.ia) put(p.ia, base, seg[5]);
+      return;
+    }
+  }
   if (!row_ok || x >= nxi) return;
   // the lane reads back only what it wrote: no barrier needed
   float o4[6][kXVec];
