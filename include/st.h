@@ -182,14 +182,15 @@ int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
  * st_batch_create validates every chunk (as st_compute would), assigns the
  * chunks to `lanes` concurrent chains (largest first, each to the chain with
  * the least work so far), gives every chain its own workspace slot and
- * captures the whole batch once into a HIP graph.  st_batch_launch replays it
- * on `stream`; replays recompute every output.  st_batch_tune (switched off in
- * this build, see below) times candidate
- * launch configurations (chain count, how far each pass splits its filtered
- * axis, graph replay vs direct multi-stream enqueue) on the real chunks and
- * keeps the fastest; results do not depend on the configuration (bitwise).
- * The chunk buffers must stay valid, and must not be written, while a launch
- * may run; chunks may not share output buffers.
+ * captures the whole batch into a HIP graph.  st_batch_launch replays it on
+ * `stream`; replays recompute every output.  st_batch_tune times candidate
+ * launch configurations on the real chunks and keeps the fastest: per chunk
+ * the tile shapes (rows of a gradient tile, lanes of a final-pass row
+ * segment), then for the whole batch the chain count, how far each pass
+ * splits its filtered axis, and graph replay vs direct multi-stream enqueue.
+ * Results do not depend on the configuration (bitwise).  The chunk buffers
+ * must stay valid, and must not be written, while a launch may run; chunks may
+ * not share output buffers.
  */
 typedef struct st_chunk {
   const void* volume;     /* device [nz][ny][nx] of dtype */
@@ -232,11 +233,15 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
 /* Enqueues the whole batch on `stream`. */
 int st_batch_launch(st_batch* batch, void* stream);
 
-/* Autotuning (switched off in this build): would time candidate
- * configurations on the real chunks and keep the fastest.  Repeated graph
- * re-capture during tuning crashed the host process intermittently, with the
- * cause not identified, so the call validates its arguments (batch non-NULL,
- * reps >= 1) and returns ST_ERR_UNSUPPORTED without touching the batch. */
+/* Autotuning, synchronous: waits for the batch's earlier launches, destroys
+ * its graph, then times on `stream` (each candidate once untimed, then `reps`
+ * times): for every chunk alone, the gradient tile rows and the final-pass
+ * segment lanes compiled for its radii; for the whole batch in direct
+ * enqueue, the chain count (1, 2, 4, 8 up to the workspace slots) and split
+ * targets (x1/4, x1, x4 around the chain count's default); finally the chosen
+ * configuration replayed from one newly captured graph against direct
+ * enqueue.  Keeps the fastest (best_ms in st_batch_config).  On an error the
+ * batch stays usable with direct enqueue.  reps >= 1. */
 int st_batch_tune(st_batch* batch, void* stream, int reps);
 
 /* Current configuration; any output pointer may be NULL.  lanes: chains in use;
@@ -245,9 +250,15 @@ int st_batch_tune(st_batch* batch, void* stream, int reps);
  * waves (one wave per tile row); strided_min_waves: the same target for the
  * integration passes (with more than one chain both are a quarter of a lone
  * st_compute's, since the chains fill the chip together); best_ms: the tuned
- * time per launch (always 0 here, since st_batch_tune is switched off). */
+ * time per launch of the configuration st_batch_tune chose (0 before tuning). */
 int st_batch_config(const st_batch* batch, int* lanes, int* use_graph, int64_t* grad_min_blocks,
                     int64_t* strided_min_waves, double* best_ms);
+
+/* Tile shapes of chunk `chunk` (0 <= chunk < nchunks): the rows of a gradient
+ * tile and the lanes of a final-pass row segment; 0 means the library's
+ * default for the chunk's radii and width (what an untuned batch uses).
+ * Either output pointer may be NULL. */
+int st_batch_tiles(const st_batch* batch, int chunk, int* grad_rows, int* final_lanes);
 
 /* Releases the batch (waits for its work to finish). */
 int st_batch_destroy(st_batch* batch);

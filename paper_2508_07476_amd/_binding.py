@@ -60,6 +60,7 @@ SIGNATURES = {
     "st_batch_tune": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "st_batch_config": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
+    "st_batch_tiles": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "st_batch_destroy": (ctypes.c_int, [_P]),
     "st_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "st_profile_reset": (ctypes.c_int, []),
@@ -147,6 +148,34 @@ def _require_device_tensor(name, t, dtypes, shape=None):
 ALL_OUTPUTS = ("e3", "evals", "fa", "ha", "ia", "flags")
 
 
+def _mask_arg(mask, shape):
+    """The mask as a uint8 device tensor of ``shape`` (a bool mask is viewed as uint8), or None."""
+    import torch
+    if mask is None:
+        return None
+    _require_device_tensor("mask", mask, (torch.uint8, torch.bool), shape)
+    return mask.view(torch.uint8) if mask.dtype == torch.bool else mask
+
+
+def _outputs(outputs, out, shape, dev):
+    """The requested st_compute outputs: tensors from ``out`` (checked) or new ones."""
+    import torch
+    outputs = tuple(outputs)
+    res = {}
+    out = out or {}
+    for k in outputs:
+        if k not in ALL_OUTPUTS:
+            raise ValueError(f"unknown output {k!r}")
+        shp = (3,) + tuple(shape) if k in ("e3", "evals") else tuple(shape)
+        dt = torch.uint8 if k == "flags" else torch.float32
+        if k in out:
+            _require_device_tensor(k, out[k], (dt,), shp)
+            res[k] = out[k]
+        else:
+            res[k] = torch.empty(shp, dtype=dt, device=dev)
+    return res
+
+
 def st_compute(volume, sigma: float, rho: float, truncate: float = 4.0, mask=None,
                axis_center=None, axis_direction=None,
                outputs: Iterable[str] = ("e3", "fa", "ha", "ia", "flags"),
@@ -167,24 +196,8 @@ def st_compute(volume, sigma: float, rho: float, truncate: float = 4.0, mask=Non
     nz, ny, nx = volume.shape
     dev = volume.device
     dtype = ST_DTYPE_U16 if volume.dtype == torch.uint16 else ST_DTYPE_F32
-    if mask is not None:
-        _require_device_tensor("mask", mask, (torch.uint8, torch.bool), (nz, ny, nx))
-        if mask.dtype == torch.bool:
-            mask = mask.view(torch.uint8)
-    outputs = tuple(outputs)
-    for k in outputs:
-        if k not in ALL_OUTPUTS:
-            raise ValueError(f"unknown output {k!r}")
-    res = {}
-    out = out or {}
-    for k in outputs:
-        shape = (3, nz, ny, nx) if k in ("e3", "evals") else (nz, ny, nx)
-        dt = torch.uint8 if k == "flags" else torch.float32
-        if k in out:
-            _require_device_tensor(k, out[k], (dt,), shape)
-            res[k] = out[k]
-        else:
-            res[k] = torch.empty(shape, dtype=dt, device=dev)
+    mask = _mask_arg(mask, (nz, ny, nx))
+    res = _outputs(outputs, out, (nz, ny, nx), dev)
     if workspace is None:
         workspace = torch.empty(st_workspace_bytes((nz, ny, nx)), dtype=torch.uint8, device=dev)
     else:
@@ -394,11 +407,16 @@ class Batch:
         _check(load_library().st_batch_launch(self._handle(), _stream_handle(self.device)))
 
     def tune(self, reps: int = 2) -> dict:
-        """Autotuning: switched off in this build (st_batch_tune returns
-        ST_ERR_UNSUPPORTED, raised here as StError); lanes=0 already selects the
-        configuration it chose in every measured run."""
+        """Autotune tile shapes (per chunk), chain count, split targets and graph
+        vs direct enqueue on the real chunks (synchronises); returns :meth:`config`."""
         _check(load_library().st_batch_tune(self._handle(), _stream_handle(self.device), int(reps)))
         return self.config()
+
+    def tiles(self, chunk: int) -> tuple:
+        """(gradient tile rows, final-pass segment lanes) of a chunk; 0 = library default."""
+        rows, lanes = ctypes.c_int(), ctypes.c_int()
+        _check(load_library().st_batch_tiles(self._handle(), int(chunk), ctypes.byref(rows), ctypes.byref(lanes)))
+        return rows.value, lanes.value
 
     def config(self) -> dict:
         lanes, graph = ctypes.c_int(), ctypes.c_int()

@@ -6,8 +6,9 @@
 // z through per-column register windows, so that
 //   g_z = Dz (Gx Gy V),  g_y = Gz (Gx Dy V),  g_x = Gz (Dx Gy V).
 // A block of TY waves owns a TY (y) x 64 (x) tile of output columns and a chunk
-// of z outputs (TY = 8 up to radius 6, where 8-row blocks still fit four waves
-// per SIMD without spilling, else 4).  For every input plane (z halo of R on
+// of z outputs (by default TY = 8 up to radius 6, where 8-row blocks still fit
+// four waves per SIMD without spilling, else 4; a 4-row variant is also built
+// up to radius 6 for the batch autotuner).  For every input plane (z halo of R on
 // each side, reflected at the faces) the (TY + 2R) x (64 + 2R) input tile is
 // staged in LDS; the next
 // plane's loads are issued before the current plane is filtered.  Each
@@ -161,9 +162,19 @@ void k_grad_fused(const GradFusedParams p) {
 template <typename Tin, int R>
 hipError_t launch_r(const GradFusedParams& p, hipStream_t stream) {
   const int64_t blocks = p.x_tiles * p.y_tiles * p.nchunks;
-  hipLaunchKernelGGL((k_grad_fused<R, Tin>), dim3(static_cast<unsigned>(blocks)), dim3(kGradTX, grad_tile_rows(R)), 0,
-                     stream, p);
-  return hipGetLastError();
+  if (p.rows == grad_tile_rows(R)) {
+    hipLaunchKernelGGL((k_grad_fused<R, Tin>), dim3(static_cast<unsigned>(blocks)), dim3(kGradTX, grad_tile_rows(R)),
+                       0, stream, p);
+    return hipGetLastError();
+  }
+  if constexpr (grad_rows_supported(R, 4) && grad_tile_rows(R) != 4) {
+    if (p.rows == 4) {
+      hipLaunchKernelGGL((k_grad_fused<R, Tin, 4>), dim3(static_cast<unsigned>(blocks)), dim3(kGradTX, 4), 0,
+                         stream, p);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace

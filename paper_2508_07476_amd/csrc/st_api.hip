@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -34,6 +35,11 @@ int fail(int code, const char* fmt, ...) {
 
 int device_fail(hipError_t e, const char* what) {
   return fail(ST_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool alloc_fault_injected() {
+  const char* v = std::getenv("ST_FAULT_INJECT");
+  return v != nullptr && std::strcmp(v, "alloc") == 0;
 }
 
 }  // namespace host
@@ -364,7 +370,8 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
       p.nz = nz; p.ny = ny; p.nx = nx;
       p.opitch = pitch;
       p.x_tiles = (nx + st::kGradTX - 1) / st::kGradTX;
-      const int64_t rows = st::grad_tile_rows(ps);
+      const int64_t rows = shape.grad_rows ? shape.grad_rows : st::grad_tile_rows(ps);
+      p.rows = static_cast<int>(rows);
       p.y_tiles = (ny + rows - 1) / rows;
       // split z until there are enough waves to fill the chip (grad_min_blocks
       // counts blocks of four waves), keeping chunks >= 8R
@@ -432,7 +439,8 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
         const int64_t t = tl * st::kXVec;
         return static_cast<double>(nx) / static_cast<double>(t * ((nx + t - 1) / t));
       };
-      p.tile_lanes = (pr <= st::kXNarrowMaxRadius && fill(16) >= fill(64) + 0.05) ? 16 : 64;
+      p.tile_lanes = shape.xfinal_lanes ? shape.xfinal_lanes
+                                        : (pr <= st::kXNarrowMaxRadius && fill(16) >= fill(64) + 0.05) ? 16 : 64;
       p.x_tiles = (nx + p.tile_lanes * st::kXVec - 1) / (p.tile_lanes * st::kXVec);
       bool vec = true;  // the kernel also checks each row's and plane's offset
       for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
@@ -487,6 +495,8 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask, int64_t nz, i
     return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
   if (workspace != nullptr && workspace_bytes < ws_need)
     return fail(ST_ERR_INVALID_ARG, "workspace_bytes %zu < required %zu", workspace_bytes, ws_need);
+  if (workspace == nullptr && st::host::alloc_fault_injected())
+    return fail(ST_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed (ST_FAULT_INJECT=alloc)", ws_need);
   if ((st = st::host::check_path_buffers(a)) != ST_OK) return st;
   if ((st = check_buffer(workspace, ws_need, "workspace")) != ST_OK) return st;
 

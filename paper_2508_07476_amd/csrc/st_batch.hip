@@ -6,10 +6,19 @@
 // the chain with the least voxels so far (longest-processing-time order); each
 // chain owns a workspace slot sized for the largest chunk and a stream of its
 // own, so small chunks that cannot fill the chip alone run side by side.  The
-// fork / join of the chains is recorded once into a HIP graph and replayed.
-// Every output is computed by the same kernels with the same per-voxel
-// summation order in every configuration, so results are bitwise independent
-// of the chain count.
+// fork / join of the chains is recorded into a HIP graph and replayed.  Every
+// output is computed by the same kernels with the same per-voxel summation
+// order in every configuration (chain count, split targets, tile shapes,
+// graph or direct enqueue), so results are bitwise independent of it.
+//
+// Lifetime rules, kept by construction:
+//  - every capture gets fork / join events of its own, created with the graph
+//    and destroyed with it; direct enqueue uses a separate set of events;
+//  - each launch waits for the previous one (on whatever stream it ran) and
+//    records `done` on its own stream, so `done` follows every launch so far;
+//    a graph is destroyed only after `done` and every stream of the batch have
+//    been waited for, so no destroyed graph or event can still be referenced
+//    by queued work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,8 +32,28 @@
 using st::host::device_fail;
 using st::host::fail;
 
+namespace {
+
+// One captured batch: the graph, its executable and the events used only by
+// its capture.
+struct Captured {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[ST_BATCH_MAX_LANES] = {};
+};
+
+// Events that order a fork / join: a capture's own, or the direct-enqueue set.
+struct ForkJoin {
+  hipEvent_t fork;
+  const hipEvent_t* join;
+};
+
+}  // namespace
+
 struct st_batch {
   std::vector<st::host::PathArgs> chunks;
+  std::vector<st::host::LaunchShape> tiles;  // per chunk: tile shapes (split targets unused)
   size_t slot_bytes = 0;  // workspace of the largest chunk
   int slots = 0;          // workspace slots (the largest chain count possible)
   char* ws = nullptr;
@@ -33,15 +62,16 @@ struct st_batch {
   // configuration
   int lanes = 1;
   bool use_graph = true;
-  st::host::LaunchShape shape;
+  st::host::LaunchShape shape;  // split targets of every chunk
   double best_ms = 0.0;
   // runtime objects
-  hipStream_t cap = nullptr;  // origin of the captured fork / join
+  hipStream_t cap = nullptr;  // origin of captures
   hipStream_t lane_stream[ST_BATCH_MAX_LANES] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[ST_BATCH_MAX_LANES] = {};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipEvent_t dfork = nullptr;  // direct enqueue
+  hipEvent_t djoin[ST_BATCH_MAX_LANES] = {};
+  hipEvent_t done = nullptr;   // recorded on the launch stream after every launch
+  bool launched = false;
+  Captured* captured = nullptr;
   std::vector<std::vector<int>> plan;  // chunk indices of every chain, in launch order
 };
 
@@ -76,65 +106,113 @@ void make_plan(st_batch* b) {
   }
 }
 
+// The launch shape of chunk i: the batch's split targets with the chunk's tiles.
+st::host::LaunchShape chunk_shape(const st_batch* b, int i) {
+  st::host::LaunchShape s = b->shape;
+  s.grad_rows = b->tiles[i].grad_rows;
+  s.xfinal_lanes = b->tiles[i].xfinal_lanes;
+  return s;
+}
+
 // Fork from `root` into the chains, enqueue every chunk, join back into `root`.
-hipError_t enqueue_all(st_batch* b, hipStream_t root, const char** stage) {
+hipError_t enqueue_all(st_batch* b, hipStream_t root, const ForkJoin& fj, const char** stage) {
   *stage = "fork";
-  hipError_t e = hipEventRecord(b->fork, root);
+  hipError_t e = hipEventRecord(fj.fork, root);
   if (e != hipSuccess) return e;
   for (int k = 0; k < b->lanes; ++k) {
     if (b->plan[k].empty()) continue;
     hipStream_t s = b->lane_stream[k];
-    if ((e = hipStreamWaitEvent(s, b->fork, 0)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, fj.fork, 0)) != hipSuccess) return e;
     char* ws = b->ws + static_cast<size_t>(k) * b->slot_bytes;
     for (int i : b->plan[k])
-      if ((e = st::host::enqueue_path(b->chunks[i], ws, s, b->shape, false, stage)) != hipSuccess) return e;
+      if ((e = st::host::enqueue_path(b->chunks[i], ws, s, chunk_shape(b, i), false, stage)) != hipSuccess)
+        return e;
     *stage = "join";
-    if ((e = hipEventRecord(b->join[k], s)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(root, b->join[k], 0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(fj.join[k], s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(root, fj.join[k], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-void drop_graph(st_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+// Waits for every launch of the batch and every stream it owns.
+hipError_t wait_idle(st_batch* b) {
+  hipError_t e = hipSuccess;
+  if (b->launched && b->done) e = hipEventSynchronize(b->done);
+  for (int k = 0; k < ST_BATCH_MAX_LANES && e == hipSuccess; ++k)
+    if (b->lane_stream[k]) e = hipStreamSynchronize(b->lane_stream[k]);
+  if (e == hipSuccess && b->cap) e = hipStreamSynchronize(b->cap);
+  return e;
 }
 
-// Re-plans for the current configuration and, in graph mode, captures the graph.
-int rebuild(st_batch* b) {
+void destroy_captured(Captured* c) {
+  if (c == nullptr) return;
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  for (hipEvent_t ev : c->join)
+    if (ev) (void)hipEventDestroy(ev);
+  delete c;
+}
+
+// Destroys the batch's graph; its launches must be known to be complete (wait_idle).
+void drop_graph(st_batch* b) {
+  destroy_captured(b->captured);
+  b->captured = nullptr;
+}
+
+// Plans for the current configuration and captures it into a new graph with
+// events of its own (the batch must hold no graph).
+int capture(st_batch* b) {
   make_plan(b);
-  drop_graph(b);
-  if (!b->use_graph) return ST_OK;
-  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return device_fail(e, "hipStreamBeginCapture");
-  const char* stage = "";
-  hipError_t ee = enqueue_all(b, b->cap, &stage);
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(b->cap, &g);  // always ends the capture, also after a failure
-  if (ee != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return device_fail(ee, stage);
-  }
-  if (e != hipSuccess) return device_fail(e, "hipStreamEndCapture");
-  b->graph = g;
-  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  Captured* c = new (std::nothrow) Captured();
+  if (c == nullptr) return fail(ST_ERR_OUT_OF_MEMORY, "host allocation failed");
+  hipError_t e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  for (int k = 0; k < b->lanes && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming);
   if (e != hipSuccess) {
-    drop_graph(b);
+    destroy_captured(c);
+    return device_fail(e, "hipEventCreateWithFlags");
+  }
+  e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    destroy_captured(c);
+    return device_fail(e, "hipStreamBeginCapture");
+  }
+  const char* stage = "";
+  hipError_t ee = enqueue_all(b, b->cap, ForkJoin{c->fork, c->join}, &stage);
+  e = hipStreamEndCapture(b->cap, &c->graph);  // always ends the capture, also after a failure
+  if (ee != hipSuccess || e != hipSuccess) {
+    destroy_captured(c);
+    return ee != hipSuccess ? device_fail(ee, stage) : device_fail(e, "hipStreamEndCapture");
+  }
+  e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    destroy_captured(c);
     return device_fail(e, "hipGraphInstantiate");
   }
+  b->captured = c;
   return ST_OK;
 }
 
+// Enqueues the batch on `stream` after the batch's previous launch, whichever
+// stream that was on (replays share the workspace and the outputs), and
+// records `done` after it, so `done` always follows every launch so far.
 int launch(st_batch* b, hipStream_t stream) {
+  hipError_t e = hipSuccess;
+  const char* stage = "hipStreamWaitEvent";
+  if (b->launched && (e = hipStreamWaitEvent(stream, b->done, 0)) != hipSuccess) return device_fail(e, stage);
+  stage = "hipGraphLaunch";
   if (b->use_graph) {
-    hipError_t e = hipGraphLaunch(b->exec, stream);
-    return e == hipSuccess ? ST_OK : device_fail(e, "hipGraphLaunch");
+    e = hipGraphLaunch(b->captured->exec, stream);
+  } else {
+    e = enqueue_all(b, stream, ForkJoin{b->dfork, b->djoin}, &stage);
   }
-  const char* stage = "";
-  hipError_t e = enqueue_all(b, stream, &stage);
-  return e == hipSuccess ? ST_OK : device_fail(e, stage);
+  if (e == hipSuccess) {
+    stage = "hipEventRecord";
+    e = hipEventRecord(b->done, stream);
+  }
+  if (e != hipSuccess) return device_fail(e, stage);
+  b->launched = true;
+  return ST_OK;
 }
 
 void release(st_batch* b) {
@@ -142,10 +220,11 @@ void release(st_batch* b) {
   drop_graph(b);
   for (int k = 0; k < ST_BATCH_MAX_LANES; ++k) {
     if (b->lane_stream[k]) (void)hipStreamDestroy(b->lane_stream[k]);
-    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    if (b->djoin[k]) (void)hipEventDestroy(b->djoin[k]);
   }
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->dfork) (void)hipEventDestroy(b->dfork);
+  if (b->done) (void)hipEventDestroy(b->done);
   if (b->owned && b->ws) (void)hipFree(b->ws);
   delete b;
 }
@@ -164,6 +243,39 @@ bool slot_plan(const st_chunk* chunks, int nchunks, size_t* slot) {
   }
   *slot = m;
   return true;
+}
+
+// ---- autotuning ---------------------------------------------------------------
+
+// Elapsed milliseconds per repetition of fn() on `stream` (one untimed run first).
+template <class F>
+int time_reps(hipStream_t stream, hipEvent_t t0, hipEvent_t t1, int reps, F&& fn, double* ms) {
+  int st = fn();
+  if (st != ST_OK) return st;
+  hipError_t e = hipEventRecord(t0, stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    if ((st = fn()) != ST_OK) return st;
+  if (e == hipSuccess) e = hipEventRecord(t1, stream);
+  if (e == hipSuccess) e = hipEventSynchronize(t1);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, t0, t1);
+  if (e != hipSuccess) return device_fail(e, "autotune timing");
+  *ms = static_cast<double>(f) / reps;
+  return ST_OK;
+}
+
+// Tile shapes worth timing for one chunk: gradient tile rows compiled for its
+// sigma radius, and final-pass segment widths compiled for its rho radius.
+void tile_candidates(const st::host::PathArgs& a, std::vector<int>* rows, std::vector<int>* lanes) {
+  const int rs = st::padded_radius(static_cast<int>(std::floor(a.truncate * a.sigma + 0.5)), true);
+  const int rr = st::padded_radius(static_cast<int>(std::floor(a.truncate * a.rho + 0.5)), false);
+  rows->clear();
+  lanes->clear();
+  if (rs <= st::kGradMaxRadius && a.ny * a.nx <= INT32_MAX)
+    for (int r : {8, 4})
+      if (st::grad_rows_supported(rs, r)) rows->push_back(r);
+  for (int l : {64, 16})
+    if (st::xfinal_lanes_supported(rr, l)) lanes->push_back(l);
 }
 
 }  // namespace
@@ -216,6 +328,9 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
     return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
   if (workspace != nullptr && workspace_bytes < need)
     return fail(ST_ERR_INVALID_ARG, "workspace_bytes %zu < required %zu", workspace_bytes, need);
+  if (workspace == nullptr && st::host::alloc_fault_injected())
+    return fail(ST_ERR_OUT_OF_MEMORY, "batch workspace allocation of %zu bytes failed (ST_FAULT_INJECT=alloc)",
+                need);
 
   // ---- device checks ----
   for (int i = 0; i < nchunks; ++i) {
@@ -230,6 +345,7 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   st_batch* b = new (std::nothrow) st_batch();
   if (b == nullptr) return fail(ST_ERR_OUT_OF_MEMORY, "host allocation failed");
   b->chunks = std::move(args);
+  b->tiles.assign(b->chunks.size(), st::host::LaunchShape{});
   b->slot_bytes = slot;
   b->slots = slots;
   b->lanes = lanes == 0 ? slots : lanes;
@@ -249,9 +365,10 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   }
   if (e == hipSuccess) {
     what = "hipEventCreateWithFlags";
-    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&b->dfork, hipEventDisableTiming);
     for (int k = 0; k < ST_BATCH_MAX_LANES && e == hipSuccess; ++k)
-      e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+      e = hipEventCreateWithFlags(&b->djoin[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   }
   if (e == hipSuccess && workspace == nullptr) {
     what = "hipMalloc (batch workspace)";
@@ -266,7 +383,7 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
     return e == hipErrorOutOfMemory ? fail(ST_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e))
                                     : device_fail(e, what);
   }
-  int st = rebuild(b);
+  int st = capture(b);
   if (st != ST_OK) {
     release(b);
     return st;
@@ -283,18 +400,108 @@ int st_batch_launch(st_batch* b, void* stream) {
   return launch(b, static_cast<hipStream_t>(stream));
 }
 
-// Switched off: repeated re-capture of the batch graph on the same streams and
-// events, mixed with direct enqueues on those events, crashed the host process
-// intermittently on the target machine and the cause is not identified.  The
-// configuration it chose in every measured run (8 chains, graph replay, default
-// split targets) is what lanes = 0 gives.
-int st_batch_tune(st_batch* b, void*, int reps) {
+int st_batch_tune(st_batch* b, void* stream_, int reps) {
   st::host::clear_error();
   if (b == nullptr) return fail(ST_ERR_INVALID_ARG, "batch is NULL");
   if (reps < 1) return fail(ST_ERR_INVALID_ARG, "reps must be >= 1");
-  return fail(ST_ERR_UNSUPPORTED,
-              "st_batch_tune is switched off in this build (an unexplained host crash during graph "
-              "re-capture); lanes = 0 selects its measured choice, 8 chains with graph replay");
+  DeviceScope dev(b->device);
+  if (dev.err != hipSuccess) return device_fail(dev.err, "hipSetDevice");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  // nothing of an earlier graph may survive: its launches finish first
+  hipError_t e = wait_idle(b);
+  if (e != hipSuccess) return device_fail(e, "waiting for the batch");
+  drop_graph(b);
+  b->use_graph = false;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return device_fail(e, "hipEventCreate");
+  }
+  int st = ST_OK;
+
+  // 1. tile shapes, chunk by chunk (alone on the stream, workspace slot 0):
+  // gradient tile rows first, then the final pass's segment width
+  std::vector<int> rows, lanes;
+  for (size_t i = 0; i < b->chunks.size() && st == ST_OK; ++i) {
+    tile_candidates(b->chunks[i], &rows, &lanes);
+    for (int which = 0; which < 2 && st == ST_OK; ++which) {
+      const std::vector<int>& cand = which == 0 ? rows : lanes;
+      if (cand.size() < 2) continue;
+      double best = INFINITY;
+      int pick = cand[0];
+      for (int v : cand) {
+        st::host::LaunchShape s = chunk_shape(b, static_cast<int>(i));
+        (which == 0 ? s.grad_rows : s.xfinal_lanes) = v;
+        double ms = 0.0;
+        st = time_reps(stream, t0, t1, reps, [&]() -> int {
+          const char* stage = "";
+          hipError_t er = st::host::enqueue_path(b->chunks[i], b->ws, stream, s, false, &stage);
+          return er == hipSuccess ? ST_OK : device_fail(er, stage);
+        }, &ms);
+        if (st != ST_OK) break;
+        if (ms < best) { best = ms; pick = v; }
+      }
+      (which == 0 ? b->tiles[i].grad_rows : b->tiles[i].xfinal_lanes) = pick;
+    }
+  }
+
+  // 2. chain count, then split targets: the whole batch, direct enqueue
+  const st::host::LaunchShape base;
+  auto time_batch = [&](int nl, double factor, double* ms) -> int {
+    b->lanes = nl;
+    b->shape.grad_min_blocks = std::max<int64_t>(1, static_cast<int64_t>(base.grad_min_blocks * factor));
+    b->shape.strided_min_waves = std::max<int64_t>(1, static_cast<int64_t>(base.strided_min_waves * factor));
+    make_plan(b);
+    return time_reps(stream, t0, t1, reps, [&] { return launch(b, stream); }, ms);
+  };
+  int best_lanes = 1;
+  double best_factor = 1.0, best_ms = INFINITY;
+  for (int nl : {1, 2, 4, 8}) {
+    if (st != ST_OK || nl > b->slots) break;
+    const double f = nl > 1 ? 0.25 : 1.0;
+    double ms = 0.0;
+    st = time_batch(nl, f, &ms);
+    if (st == ST_OK && ms < best_ms) { best_ms = ms; best_lanes = nl; best_factor = f; }
+  }
+  const double f0 = best_factor;
+  for (double f : {f0 / 4, f0 * 4}) {
+    if (st != ST_OK) break;
+    double ms = 0.0;
+    st = time_batch(best_lanes, f, &ms);
+    if (st == ST_OK && ms < best_ms) { best_ms = ms; best_factor = f; }
+  }
+
+  // 3. the chosen configuration replayed from one graph, against direct enqueue
+  if (st == ST_OK) {
+    double direct_ms = 0.0, graph_ms = 0.0;
+    st = time_batch(best_lanes, best_factor, &direct_ms);
+    if (st == ST_OK) st = capture(b);
+    if (st == ST_OK) {
+      b->use_graph = true;
+      st = time_reps(stream, t0, t1, reps, [&] { return launch(b, stream); }, &graph_ms);
+    }
+    if (st == ST_OK) {
+      b->best_ms = std::min(direct_ms, graph_ms);
+      if (direct_ms < graph_ms) {
+        e = wait_idle(b);
+        if (e != hipSuccess) st = device_fail(e, "waiting for the batch");
+        drop_graph(b);
+        b->use_graph = false;
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st != ST_OK) {
+    // leave a usable batch: direct enqueue of whatever configuration was set
+    (void)wait_idle(b);
+    drop_graph(b);
+    b->use_graph = false;
+    make_plan(b);
+  }
+  return st;
 }
 
 int st_batch_config(const st_batch* b, int* lanes, int* use_graph, int64_t* grad_min_blocks,
@@ -309,15 +516,23 @@ int st_batch_config(const st_batch* b, int* lanes, int* use_graph, int64_t* grad
   return ST_OK;
 }
 
+int st_batch_tiles(const st_batch* b, int chunk, int* grad_rows, int* final_lanes) {
+  st::host::clear_error();
+  if (b == nullptr) return fail(ST_ERR_INVALID_ARG, "batch is NULL");
+  if (chunk < 0 || chunk >= static_cast<int>(b->chunks.size()))
+    return fail(ST_ERR_INVALID_ARG, "chunk %d is outside 0..%d", chunk, static_cast<int>(b->chunks.size()) - 1);
+  if (grad_rows) *grad_rows = b->tiles[chunk].grad_rows;
+  if (final_lanes) *final_lanes = b->tiles[chunk].xfinal_lanes;
+  return ST_OK;
+}
+
 int st_batch_destroy(st_batch* b) {
   st::host::clear_error();
   if (b == nullptr) return ST_OK;
   DeviceScope dev(b->device);
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < ST_BATCH_MAX_LANES && e == hipSuccess; ++k)
-    if (b->lane_stream[k]) e = hipStreamSynchronize(b->lane_stream[k]);
+  hipError_t e = wait_idle(b);
   release(b);
-  return e == hipSuccess ? ST_OK : device_fail(e, "hipStreamSynchronize");
+  return e == hipSuccess ? ST_OK : device_fail(e, "waiting for the batch");
 }
 
 }  // extern "C"

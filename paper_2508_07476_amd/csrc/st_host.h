@@ -16,6 +16,10 @@ namespace host {
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int device_fail(hipError_t e, const char* what);
 void clear_error();
+// True when the environment variable ST_FAULT_INJECT is "alloc": every library
+// allocation of device memory is then reported as failed (ST_ERR_OUT_OF_MEMORY)
+// before any HIP call, so tests can exercise that path on any machine.
+bool alloc_fault_injected();
 
 // One volume through the whole path, validated.
 struct PathArgs {
@@ -42,9 +46,15 @@ struct PathArgs {
 // against the filter radius).  Every gradient piece re-reads 2R halo planes, so
 // the split stops at four waves per SIMD: a 512^3 volume's x-y tiles already
 // fill the chip.  A batch of concurrent chains uses a quarter of both targets.
+// Tile shapes: grad_rows (output rows per gradient block) and xfinal_lanes
+// (lanes per row segment of the final pass); 0 takes the library's default for
+// the radius and width, other values must be compiled for the radius
+// (grad_rows_supported, xfinal_lanes_supported).
 struct LaunchShape {
   int64_t grad_min_blocks = 1024;
   int64_t strided_min_waves = 16384;
+  int grad_rows = 0;
+  int xfinal_lanes = 0;
 };
 
 // Sizes each in [1, 2^31) with every byte count of the path fitting: *n is the

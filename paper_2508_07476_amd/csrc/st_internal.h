@@ -114,6 +114,10 @@ struct XFinalParams {
 constexpr int kXVec = 4;                 // consecutive x outputs per lane
 constexpr int kXTile = 64 * kXVec;       // x outputs per wave (one row segment of 64 lanes)
 constexpr int kXNarrowMaxRadius = 16;    // radii with 16-lane segments of the final pass
+// Lanes per row segment of the final pass compiled for radius R.
+constexpr bool xfinal_lanes_supported(int R, int lanes) {
+  return lanes == 64 || (lanes == 16 && R <= kXNarrowMaxRadius);
+}
 constexpr int kRowsPerBlock = 4;         // rows per block of the angle kernel (one per wave)
 
 hipError_t launch_xgrad(int R, const XGradParams& p, hipStream_t stream);
@@ -132,13 +136,18 @@ struct GradFusedParams {
   int64_t x_tiles, y_tiles;
   int64_t chunk;      // z outputs per block
   int nchunks;
+  int rows;           // output rows (y) per block, one wave each: grad_rows_supported(R, rows)
   Taps wg;
   Taps wd;
 };
 constexpr int kGradTX = 64;
-// Output rows per block (one wave per row): 8 where the kernel fits four waves
-// per SIMD without spilling, else 4.
+// Output rows per block (one wave per row) by default: 8 where the kernel fits
+// four waves per SIMD without spilling, else 4.
 constexpr int grad_tile_rows(int R) { return R <= 6 ? 8 : 4; }
+// Tile rows compiled for radius R: the default, and 4 rows up to radius 6 too.
+constexpr bool grad_rows_supported(int R, int rows) {
+  return rows == grad_tile_rows(R) || (rows == 4 && R <= 6);
+}
 constexpr int kGradMaxRadius = 8;  // larger sigma radii use the three separate passes
 hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream);
 

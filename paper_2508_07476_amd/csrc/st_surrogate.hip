@@ -46,6 +46,8 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
   if (!has_axis && (ha != nullptr || ia != nullptr))
     return fail(ST_ERR_INVALID_ARG, "ha / ia need an axis (axis_center and axis_direction)");
   if (!e3 && !fa && !ha && !ia && !confidence) return fail(ST_ERR_INVALID_ARG, "no output requested");
+  if (st::host::alloc_fault_injected())
+    return fail(ST_ERR_OUT_OF_MEMORY, "surrogate workspace allocation failed (ST_FAULT_INJECT=alloc)");
 
   // ---- device buffer checks ----
   const size_t N = static_cast<size_t>(n);

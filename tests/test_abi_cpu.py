@@ -220,4 +220,58 @@ def test_batch_calls_reject_null_handle(lib):
     assert lib.st_batch_launch(None, None) == B.ST_ERR_INVALID_ARG
     assert lib.st_batch_tune(None, None, 1) == B.ST_ERR_INVALID_ARG
     assert lib.st_batch_config(None, None, None, None, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_batch_tiles(None, 0, None, None) == B.ST_ERR_INVALID_ARG
     assert lib.st_batch_destroy(None) == B.ST_OK
+
+
+# ---- forced allocation failure (ST_FAULT_INJECT=alloc) ----------------------
+# With the hook set, each entry point that would allocate device memory reports
+# ST_ERR_OUT_OF_MEMORY after host validation and before any HIP call, so the
+# path runs on a machine without a GPU.  The outputs here are host buffers with
+# a sentinel: the library must not write them.
+
+
+def _sentinel(n):
+    buf = (ctypes.c_float * n)(*([7.25] * n))
+    return buf, ctypes.cast(buf, ctypes.c_void_p)
+
+
+def _untouched(buf):
+    return all(v == 7.25 for v in buf)
+
+
+def test_fault_inject_alloc_compute(lib, monkeypatch):
+    monkeypatch.setenv("ST_FAULT_INJECT", "alloc")
+    buf, ptr = _sentinel(3 * 8 * 8 * 8)
+    code, msg = _compute(lib, e3=ptr)  # workspace NULL: the library would allocate it
+    assert code == B.ST_ERR_OUT_OF_MEMORY, msg
+    assert "ST_FAULT_INJECT" in msg and _untouched(buf)
+    # a caller workspace needs no allocation: the hook does not fire (the call
+    # then fails at the device-buffer check, since nothing here is on a GPU)
+    code, msg = _compute(lib, e3=ptr, ws=FAKE, ws_bytes=1 << 20)
+    assert code != B.ST_ERR_OUT_OF_MEMORY and "ST_FAULT_INJECT" not in msg
+    assert _untouched(buf)
+
+
+def test_fault_inject_alloc_batch_create(lib, monkeypatch):
+    monkeypatch.setenv("ST_FAULT_INJECT", "alloc")
+    buf, ptr = _sentinel(3 * 8 * 8 * 8)
+    code, msg = _create(lib, _chunks(dict(e3=ptr.value), dict(e3=ptr.value, nz=12)), 2, lanes=2)
+    assert code == B.ST_ERR_OUT_OF_MEMORY, msg
+    assert "ST_FAULT_INJECT" in msg and _untouched(buf)
+
+
+def test_fault_inject_alloc_surrogate(lib, monkeypatch):
+    monkeypatch.setenv("ST_FAULT_INJECT", "alloc")
+    buf, ptr = _sentinel(3 * 8 * 8 * 8)
+    cbuf, cptr = _sentinel(8 * 8 * 8)
+    for minc in (0.0, 0.9):
+        code, msg = _surrogate(lib, e3=ptr, conf=cptr, minc=minc)
+        assert code == B.ST_ERR_OUT_OF_MEMORY, msg
+        assert "ST_FAULT_INJECT" in msg and _untouched(buf) and _untouched(cbuf)
+
+
+def test_fault_inject_needs_the_exact_value(lib, monkeypatch):
+    monkeypatch.setenv("ST_FAULT_INJECT", "none")
+    code, msg = _compute(lib)
+    assert code != B.ST_ERR_OUT_OF_MEMORY and "ST_FAULT_INJECT" not in msg
