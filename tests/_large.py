@@ -91,7 +91,9 @@ def time_full(ph, res, reps=3):
 
 
 def block_origins(count, B, seed=2):
-    """Sub-blocks spread over the three noise bands (z thirds) and both annuli, plus the last corner."""
+    """Sub-blocks spread over the three noise bands (z thirds) and both annuli,
+    plus one against the far z face (z = nz - B) inside the outer annulus,
+    which takes the reflection at that face and the largest output indices."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = SHAPE
     c = (ny - 1) / 2.0
@@ -104,5 +106,6 @@ def block_origins(count, B, seed=2):
         y = int(np.clip(c + r * np.sin(th) - B / 2, 0, ny - B))
         x = int(np.clip(c + r * np.cos(th) - B / 2, 0, nx - B))
         out.append((z, y, x))
-    out.append((nz - B, ny - B, nx - B))
+    th = np.pi / 4  # on the outer annulus' mid-radius, in the high-y, high-x quadrant
+    out.append((nz - B, int(c + 400.0 * np.sin(th) - B / 2), int(c + 400.0 * np.cos(th) - B / 2)))
     return out

@@ -24,6 +24,7 @@ def test_two_annuli_full_size_sampled_blocks():
     for org in block_origins(4, 64):
         stats, _ = compare_block(ph, res, org, 64)
         log(org, summary(stats))
+        assert stats["n_checked"] > 0, org  # every block lies in an annulus
         assert_parity(stats, f"block {org}")
         checked += stats["n_checked"]
     assert checked > 0.3 * 4 * 64 ** 3
