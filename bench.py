@@ -1,14 +1,24 @@
 """Benchmark of the voxel-wise structure-tensor path on one MI355X.
 
-Workload: the 512^3 uint16 helical phantom with its binary annulus mask,
-sigma = 1.5, rho = 4 (truncate 4), outputs e3 + FA + HA + IA for every voxel.
-One step = one st_compute call over the whole volume, inputs resident in HBM.
-Prints one JSON line (see the "metric" key) with a roofline object for the
-dominant kernel (durations from HIP events recorded around every kernel on
-the launch stream inside the timed region) and the FP64 CPU oracle timed on a
-bounded crop of the same phantom.
+Default workload: the 2048 x 1024 x 1024 uint16 two-annuli helical phantom
+(2^31 voxels, noise 0.02 / 0.1 / 0.2 by z-thirds), sigma = 2, rho = 6
+(truncate 4), outputs e3 + FA + HA + IA for every voxel.  One step = one
+st_compute call over the whole volume, inputs, outputs and workspace resident
+in HBM.  Prints one JSON line (see the "metric" key) with
 
-  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+  * "roofline": the dominant kernel against the roof that binds it, from HIP
+    events recorded around every kernel on its launch stream inside the timed
+    region; "traffic" comes from committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters (profiles/traffic_<workload>.json) when they belong to the current
+    kernel sources, else null;
+  * "cpu_baseline": the FP64 CPU oracle on 16 sampled 96^3 blocks (each padded
+    by R_sigma + R_rho) of the same volume, one block per worker process, over
+    the host cores given to this process (at most 16);
+  * "headline512": the 512^3 uint16 phantom with its annulus mask (sigma 1.5,
+    rho 4), timed after the main workload (not part of "value").
+
+  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+                  [--workload two_annuli|headline512] [--batch] [--surrogate]
 """
 
 from __future__ import annotations
@@ -25,22 +35,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gvoxels/s (HBM GB/s vs peak) plain vs surrogate at ≤2° fibre-angle error"
 HBM_PEAK_GBS = 8000.0
-
-SHAPE = (512, 512, 512)
-SIGMA, RHO, TRUNCATE = 1.5, 4.0, 4.0
+TRUNCATE = 4.0
 OUTPUTS = ("e3", "fa", "ha", "ia")
 
-# Algorithmic HBM bytes per voxel and per launch of each kernel (input read once,
-# output written once; no halo re-reads), for this workload.
-ALG_BYTES_PER_VOXEL = {
-    "grad_fused": 2 + 24,             # u16 in, 6 products out
-    "grad_z": 2 + 8,                  # u16 in, G_z V and D_z V out
-    "grad_y": (4 + 8 + 4 + 4) / 2,    # two launches: (1 in, 2 out) and (1 in, 1 out)
-    "grad_x_outer": 12 + 24,          # 3 planes in, 6 products out
-    "integrate_z": 24 + 24,
-    "integrate_y": 24 + 24,
-    "integrate_x_eigen": 24 + 1 + 12 + 12,  # S + mask in; e3, FA, HA, IA out
+WORKLOADS = {
+    "two_annuli": {
+        "desc": "2048x1024x1024 uint16 two-annuli helical rod-lattice phantom (r 128-256: +60 to -60 deg, "
+                "r 320-480: -60 to +60 deg; noise 0.02/0.1/0.2 by z-thirds), no mask, sigma=2, rho=6, "
+                "truncate=4; outputs e3, FA, HA, IA",
+        "shape": (2048, 1024, 1024), "sigma": 2.0, "rho": 6.0, "mask": False,
+    },
+    "headline512": {
+        "desc": "512^3 uint16 helical rod-lattice phantom + annulus mask (r 96-224), sigma=1.5, rho=4, "
+                "truncate=4; outputs e3, FA, HA, IA",
+        "shape": (512, 512, 512), "sigma": 1.5, "rho": 4.0, "mask": True,
+    },
 }
+SHAPE = WORKLOADS["headline512"]["shape"]  # the batch and surrogate workloads crop this phantom
+
+
+def make_phantom(helix, workload, dev):
+    spec = (helix.spec_two_annuli_u16(shape=WORKLOADS[workload]["shape"]) if workload == "two_annuli"
+            else helix.spec_headline_u16(shape=WORKLOADS[workload]["shape"]))
+    return helix.generate(spec, device=dev)
+
+
+def alg_bytes_per_voxel(kernel, mask=False):
+    """Algorithmic HBM bytes per voxel of one launch of ``kernel``: every input
+    read once and every output written once, no halo re-reads (uint16 input,
+    float32 intermediates, outputs e3 + FA + HA + IA)."""
+    return {"grad_fused": 2 + 24,             # u16 in, 6 products out
+            "grad_z": 2 + 8,                  # u16 in, G_z V and D_z V out
+            "grad_y": (4 + 8 + 4 + 4) / 2,    # two launches: (1 in, 2 out) and (1 in, 1 out)
+            "grad_x_outer": 12 + 24,          # 3 planes in, 6 products out
+            "integrate_z": 24 + 24,
+            "integrate_y": 24 + 24,
+            "integrate_x_eigen": 24 + (1 if mask else 0) + 12 + 12,  # S (+ mask) in; e3, FA, HA, IA out
+            }[kernel]
+
+
 # Algorithmic vector-ALU operations per voxel (one FMA or one float32 op = one
 # lane-operation = 2 flop-equivalents): separable filters 2R+1 FMAs per 1-D
 # pass (8 gradient passes at sigma, 6 components per integration axis at rho),
@@ -59,9 +92,9 @@ def alg_ops_per_voxel(kernel, rs, rr):
 # (float64 FMA and non-packed float32 issue at the same rate), i.e. 78.6 TFLOP/s
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 
-# Sources the headline path is built from: kernels, their launch shapes and
-# the host layer that enqueues them.  The HBM byte counts recorded under
-# profiles/ hold for the sources with this hash.
+# Sources the plain path is built from: kernels, their launch shapes and the
+# host layer that enqueues them.  The HBM byte counts recorded under profiles/
+# hold for the sources with this hash.
 KERNEL_SOURCES = ["k_gradf.hip", "k_strided.hip", "k_strided_impl.h", "k_strided_inst.hip",
                   "k_xfinala.hip", "k_xfinalb.hip", "k_xpass.hip", "k_xpass_impl.h", "st_device.h", "st_internal.h",
                   "st_host.h", "st_api.hip"]
@@ -104,9 +137,14 @@ def kernel_source_hash(read=None):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
-    path = os.path.join(ROOT, "profiles", "traffic_headline.json")
+def traffic_path(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def traffic_for(kernel, workload="two_annuli"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    ``workload``, if it belongs to the current kernel sources (else None)."""
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -117,17 +155,17 @@ def traffic_for(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def kernel_report(kern, nvox, steps, rs, rr):
+def kernel_report(kern, nvox, steps, rs, rr, mask=False, workload="two_annuli"):
     """Roofline object of the dominant kernel and per-kernel figures.
 
     kern maps a kernel name to (total ms, launches) over `steps` steps of an
-    nvox-voxel volume; rs and rr are the gradient and integration radii.  The
-    dominant kernel is placed against whichever roof (HBM bytes or vector-ALU
-    operations) it is closer to."""
+    nvox-voxel volume; rs and rr are the gradient and integration radii; mask
+    says whether the final pass reads a mask.  The dominant kernel is placed
+    against whichever roof (HBM bytes or vector-ALU operations) it is closer to."""
 
     def roof_for(name, ms, launches):
         avg_s = ms / launches / 1e3
-        gbs = ALG_BYTES_PER_VOXEL[name] * nvox / avg_s / 1e9
+        gbs = alg_bytes_per_voxel(name, mask) * nvox / avg_s / 1e9
         ops = alg_ops_per_voxel(name, rs, rr)
         tflops = None if ops is None else ops * 2 * nvox / avg_s / 1e12
         return avg_s, gbs, ops, tflops
@@ -136,22 +174,27 @@ def kernel_report(kern, nvox, steps, rs, rr):
     avg_s, gbs, ops, tflops = roof_for(dname, dms, dlaunch)
     hbm_frac = gbs / HBM_PEAK_GBS
     alu_frac = None if tflops is None else tflops / VALU_PEAK_TFLOPS
-    common = {"traffic": traffic_for(dname), "kernel": dname, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    traffic = traffic_for(dname, workload)
+    common = {"traffic": traffic, "kernel": dname, "avg_launch_ms": round(avg_s * 1e3, 4),
+              "traffic_source": (f"committed rocprofv3 FETCH_SIZE/WRITE_SIZE counters of this workload and "
+                                 f"these kernel sources (profiles/traffic_{workload}.json), not measured in "
+                                 "this run" if traffic is not None else
+                                 "none: no committed counters for the current kernel sources")}
     if alu_frac is not None and alu_frac > hbm_frac:
         roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": round(VALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(alu_frac, 4), **common,
                 "alg_ops_per_voxel": ops, "hbm_achieved_GBps": round(gbs, 1),
-                "hbm_frac": round(hbm_frac, 4), "alg_bytes_per_voxel": ALG_BYTES_PER_VOXEL[dname]}
+                "hbm_frac": round(hbm_frac, 4), "alg_bytes_per_voxel": alg_bytes_per_voxel(dname, mask)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4), **common,
-                "alg_bytes_per_voxel": ALG_BYTES_PER_VOXEL[dname]}
+                "alg_bytes_per_voxel": alg_bytes_per_voxel(dname, mask)}
     per_kernel = {}
     for k, v in kern.items():
         a_s, g, o, t = roof_for(k, v[0], v[1])
         per_kernel[k] = {"avg_ms": round(a_s * 1e3, 4), "launches_per_step": v[1] / steps,
                          "alg_GBps": round(g, 1), "hbm_frac": round(g / HBM_PEAK_GBS, 4)}
-        tb = traffic_for(k)  # rocprofv3 bytes per launch, when current
+        tb = traffic_for(k, workload)  # rocprofv3 bytes per launch, when current
         if tb is not None:
             per_kernel[k]["measured_GBps"] = round(tb / a_s / 1e9, 1)
             per_kernel[k]["measured_frac"] = round(tb / a_s / 1e9 / HBM_PEAK_GBS, 4)
@@ -160,75 +203,165 @@ def kernel_report(kern, nvox, steps, rs, rr):
     return roof, per_kernel
 
 
-def cpu_baseline(vol_u16, mask_u8, center, direction):
-    """FP64 oracle on a bounded crop of the same phantom (single process)."""
-    import numpy as np
-    import psutil
-
+def _oracle_block(crop, mask, lo, sigma, rho, center, direction):
+    """One padded block through the FP64 oracle (runs in a worker process)."""
     import oracle
-    s = 208
-    z0, y0, x0 = 176, 96, 176
-    crop = vol_u16[z0:z0 + s, y0:y0 + s, x0:x0 + s].cpu().numpy()
-    mcrop = mask_u8[z0:z0 + s, y0:y0 + s, x0:x0 + s].cpu().numpy()
-    proc = psutil.Process()
-    c0 = proc.cpu_times()
-    t0 = time.perf_counter()
-    oracle.compute(crop, mcrop, SIGMA, RHO, TRUNCATE, axis_center=center, axis_direction=direction,
-                   origin=(z0, y0, x0))
-    wall = time.perf_counter() - t0
-    c1 = proc.cpu_times()
-    cpu = (c1.user - c0.user) + (c1.system - c0.system)
-    nvox = crop.size
-    return {"value": nvox / wall / 1e9, "unit": "Gvoxels/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": f"{s}^3 crop at (z,y,x)=({z0},{y0},{x0}) of the same phantom+mask, whole path "
-                      f"(tensor, eigen, FA, HA, IA) in FP64 NumPy, {nvox} voxels in {wall:.1f} s"}
+    oracle.compute(crop, mask, sigma, rho, TRUNCATE, axis_center=center, axis_direction=direction,
+                   origin=tuple(lo))
+    return crop.size
 
 
-def run_large(args, torch, st, helix, dev):
-    """2048 x 1024 x 1024 uint16 two-annuli volume (2^31 voxels), sigma 2, rho 6,
-    outputs e3, FA, HA, IA, flags; inputs, outputs and workspace resident."""
-    shape = (2048, 1024, 1024)
-    spec = helix.spec_two_annuli_u16(shape=shape)
-    ph = helix.generate(spec, device=dev)
+def _warm_worker(_):
+    """Imports the oracle in a worker process before the timed region."""
+    import numpy  # noqa: F401
+    import scipy.ndimage  # noqa: F401
+
+    import oracle  # noqa: F401
+    return os.getpid()
+
+
+def host_cores():
+    """(cores this process may run on, capped at 16: the host share of one GPU; CPU model)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, min(16, avail)), model
+
+
+def block_origins(shape, B, halo, count=16, seed=5, annuli=((128.0, 256.0), (320.0, 480.0))):
+    """``count`` B^3 block origins spread over the z-thirds (the noise bands) and
+    over the annuli, each at least ``halo`` from the volume faces."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    c = (ny - 1) / 2.0
+    out = []
+    for i in range(count):
+        band = i % 3
+        zlo = max(halo, band * nz // 3)
+        zhi = min(nz - B - halo, (band + 1) * nz // 3 - B)
+        z = int(rng.integers(zlo, max(zlo + 1, zhi)))
+        r_in, r_out = annuli[i % len(annuli)]
+        r = rng.uniform(r_in + B / 2, r_out - B / 2) if r_out - r_in > B else 0.5 * (r_in + r_out)
+        th = rng.uniform(0, 2 * np.pi)
+        y = int(np.clip(c + r * np.sin(th) - B / 2, halo, ny - B - halo))
+        x = int(np.clip(c + r * np.cos(th) - B / 2, halo, nx - B - halo))
+        out.append((z, y, x))
+    return out
+
+
+def cpu_baseline(workload, vol, mask, center, direction, B=96, count=16):
+    """FP64 oracle, timed on ``count`` sampled B^3 blocks of the same volume, each
+    padded by R_sigma + R_rho (which makes every block's interior equal to the
+    whole-volume result), one block per worker process over the host cores."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    w = WORKLOADS[workload]
+    sigma, rho = w["sigma"], w["rho"]
+    halo = int(TRUNCATE * sigma + 0.5) + int(TRUNCATE * rho + 0.5)
+    annuli = ((128.0, 256.0), (320.0, 480.0)) if workload == "two_annuli" else ((96.0, 224.0),)
+    s = vol.shape[1] / 1024.0 if workload == "two_annuli" else vol.shape[1] / 512.0
+    annuli = tuple((a * s, b * s) for a, b in annuli)
+    origins = block_origins(tuple(vol.shape), B, halo, count, annuli=annuli)
+    jobs = []
+    for org in origins:
+        lo = [o - halo for o in org]
+        sl = tuple(slice(lo[d], org[d] + B + halo) for d in range(3))
+        jobs.append((vol[sl].cpu().numpy(), None if mask is None else mask[sl].cpu().numpy(), lo))
+    cores, model = host_cores()
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"  # one thread per worker process
+    try:
+        with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("spawn")) as pool:
+            pids = set(pool.map(_warm_worker, range(cores)))  # start and import in every worker
+            t0 = time.perf_counter()
+            futs = [pool.submit(_oracle_block, c, m, lo, sigma, rho, center, direction) for c, m, lo in jobs]
+            padded = sum(f.result() for f in futs)
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    nvox = count * B ** 3
+    return {"value": nvox / wall / 1e9, "unit": "Gvoxels/s", "cores": min(cores, count), "kind": "oracle",
+            "cpu_model": model, "os_cpu_count": os.cpu_count(), "workers": len(pids),
+            "sample": f"{count} blocks of {B}^3 voxels of the same volume (z-thirds and annuli), each padded by "
+                      f"R_sigma + R_rho = {halo} and run whole through the FP64 NumPy/SciPy oracle (tensor, eigen, "
+                      f"FA, HA, IA), one block per single-threaded worker process; value counts the {nvox} "
+                      f"interior voxels ({padded} computed with the halos) over {wall:.1f} s wall"}
+
+
+def run_plain(args, torch, st, helix, dev, workload):
+    """One st_compute call per step on the whole volume of ``workload`` (inputs,
+    outputs and workspace resident); returns the JSON line as a dict."""
+    w = WORKLOADS[workload]
+    shape, sigma, rho = w["shape"], w["sigma"], w["rho"]
+    t = time.perf_counter()
+    ph = make_phantom(helix, workload, dev)
+    torch.cuda.synchronize()
+    print(f"bench: {workload} phantom {shape} generated in {time.perf_counter() - t:.1f} s", file=sys.stderr,
+          flush=True)
     vol = ph["volume"]
+    mask = ph["mask"] if w["mask"] else None
     nvox = vol.numel()
-    outs = ("e3", "fa", "ha", "ia", "flags")
-    out = {k: torch.empty(((3,) if k == "e3" else ()) + shape, dtype=torch.uint8 if k == "flags" else torch.float32,
-                          device=dev) for k in outs}
+    out = {k: torch.empty(((3,) if k == "e3" else ()) + tuple(shape), dtype=torch.float32, device=dev)
+           for k in OUTPUTS}
     ws = torch.empty(st.st_workspace_bytes(shape), dtype=torch.uint8, device=dev)
 
     def step():
-        st.st_compute(vol, 2.0, 6.0, TRUNCATE, axis_center=ph["center"], axis_direction=ph["direction"],
-                      outputs=outs, out=out, workspace=ws)
+        st.st_compute(vol, sigma, rho, TRUNCATE, mask=mask, axis_center=ph["center"],
+                      axis_direction=ph["direction"], outputs=OUTPUTS, out=out, workspace=ws)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
     st.profile_reset()
     st.profile_enable(True)
-    ev[0].record(stream)
+    torch.cuda.synchronize()
+    t_start.record(stream)
     for _ in range(args.steps):
         step()
-    ev[1].record(stream)
+    t_end.record(stream)
     torch.cuda.synchronize()
     st.profile_enable(False)
-    kern = {k: {"avg_ms": round(v[0] / v[1], 3), "launches_per_step": v[1] / args.steps}
-            for k, v in st.profile_read().items()}
-    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    kern = st.profile_read()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    value = nvox * args.steps / (total_ms / 1e3) / 1e9
+    rs, rr = int(TRUNCATE * sigma + 0.5), int(TRUNCATE * rho + 0.5)
+    roof, per_kernel = kernel_report(kern, nvox, args.steps, rs, rr, w["mask"], workload)
     line = {
-        "metric": METRIC, "value": round(nvox / ms / 1e6, 4), "unit": "Gvoxels/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "metric": METRIC, "value": round(value, 4), "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2048x1024x1024 uint16 two-annuli helical phantom (noise 0.02/0.1/0.2 by "
-                               "z-thirds), sigma=2, rho=6, truncate=4; outputs e3, FA, HA, IA, flags",
-                   "shape": list(shape), "arithmetic": "f64", "intermediate_storage": "f32"},
-        "kernels": kern,
+        "config": {"workload": w["desc"], "shape": list(shape), "sigma": sigma, "rho": rho, "input": "uint16",
+                   "mask": w["mask"], "arithmetic": "f64", "intermediate_storage": "f32"},
+        "roofline": roof,
+        "kernels": per_kernel,
     }
-    print(json.dumps(line), flush=True)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(workload, vol, mask, ph["center"], ph["direction"])
+    del out, ws, vol, mask, ph
+    torch.cuda.empty_cache()
+    return line
 
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2508_07476_amd", "surrogate_weights.npy")
@@ -239,6 +372,7 @@ def run_surrogate(args, torch, st, helix, dev):
     result) against the plain path on the 512^3 headline volume: throughput and the
     fibre-angle error w.r.t. the plain path inside the mask, non-degenerate voxels."""
     import numpy as np
+    sigma, rho = WORKLOADS["headline512"]["sigma"], WORKLOADS["headline512"]["rho"]
     blob = np.load(args.weights or SURROGATE_WEIGHTS, allow_pickle=False).astype(np.float32)
     w = torch.from_numpy(blob).to(dev)
     spec = helix.spec_headline_u16(shape=SHAPE)
@@ -246,7 +380,7 @@ def run_surrogate(args, torch, st, helix, dev):
     vol, mask = ph["volume"], ph["mask"]
     nvox = vol.numel()
     kw = dict(mask=mask, axis_center=ph["center"], axis_direction=ph["direction"])
-    plain = st.st_compute(vol, SIGMA, RHO, TRUNCATE, outputs=("e3", "fa", "flags"), **kw)
+    plain = st.st_compute(vol, sigma, rho, TRUNCATE, outputs=("e3", "fa", "flags"), **kw)
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
@@ -270,7 +404,7 @@ def run_surrogate(args, torch, st, helix, dev):
     res = {}
     for name, thr in (("surrogate", 0.0), ("fallback_0.9", 0.9)):
         out = {}
-        ms, kern = timed(lambda: out.update(st.st_surrogate_infer(vol, w, thr, SIGMA, RHO, TRUNCATE,
+        ms, kern = timed(lambda: out.update(st.st_surrogate_infer(vol, w, thr, sigma, rho, TRUNCATE,
                                                                   outputs=outs, **kw)))
         sel = (plain["flags"] == 0)
         a = out["e3"][:, sel].double()
@@ -285,7 +419,7 @@ def run_surrogate(args, torch, st, helix, dev):
                      "fallback_fraction": round(fell, 4), "kernels": kern}
         sur = out
     del sur
-    pms, pkern = timed(lambda: st.st_compute(vol, SIGMA, RHO, TRUNCATE, outputs=("e3", "fa", "ha", "ia"), **kw))
+    pms, pkern = timed(lambda: st.st_compute(vol, sigma, rho, TRUNCATE, outputs=("e3", "fa", "ha", "ia"), **kw))
     line = {
         "metric": METRIC, "value": res["surrogate"]["value"], "unit": "Gvoxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["surrogate"]["ms_per_step"],
@@ -372,15 +506,17 @@ def run_batch(args, torch, st, helix, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="two_annuli",
+                    help="volume timed for the line's value (default: the 2048x1024x1024 two-annuli volume)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 512^3 figure that follows the default workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
-    ap.add_argument("--large", action="store_true",
-                    help="time the 2048x1024x1024 uint16 two-annuli volume (sigma 2, rho 6)")
     ap.add_argument("--surrogate", action="store_true",
-                    help="time the learned surrogate (bf16 3-D CNN) on the headline volume and "
+                    help="time the learned surrogate (bf16 3-D CNN) on the 512^3 volume and "
                          "report its fibre-angle error against the structure-tensor path")
     ap.add_argument("--weights", default=None, help="surrogate weights (.npy, float32 blob)")
     ap.add_argument("--batch", action="store_true",
@@ -414,59 +550,15 @@ def main():
         return run_batch(args, torch, st, helix, dev)
     if args.surrogate:
         return run_surrogate(args, torch, st, helix, dev)
-    if args.large:
-        return run_large(args, torch, st, helix, dev)
-    spec = helix.spec_headline_u16(shape=SHAPE)
-    ph = helix.generate(spec, device=dev)
-    vol, mask = ph["volume"], ph["mask"]
-    nvox = vol.numel()
-    nz, ny, nx = SHAPE
-    out = {k: torch.empty(((3,) if k == "e3" else ()) + SHAPE, dtype=torch.float32, device=dev)
-           for k in OUTPUTS}
-    ws = torch.empty(st.st_workspace_bytes(SHAPE), dtype=torch.uint8, device=dev)
-
-    def step():
-        st.st_compute(vol, SIGMA, RHO, TRUNCATE, mask=mask, axis_center=ph["center"],
-                      axis_direction=ph["direction"], outputs=OUTPUTS, out=out, workspace=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    st.profile_reset()
-    st.profile_enable(True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        step()
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    st.profile_enable(False)
-    kern = st.profile_read()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / args.steps
-    value = nvox * args.steps / (total_ms / 1e3) / 1e9
-
-    roof, per_kernel = kernel_report(kern, nvox, args.steps, int(TRUNCATE * SIGMA + 0.5),
-                                     int(TRUNCATE * RHO + 0.5))
-
-    line = {
-        "metric": METRIC, "value": round(value, 4), "unit": "Gvoxels/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "512^3 uint16 helical rod-lattice phantom + annulus mask, sigma=1.5, "
-                               "rho=4, truncate=4; outputs e3, FA, HA, IA (plain path)",
-                   "shape": list(SHAPE), "sigma": SIGMA, "rho": RHO, "input": "uint16",
-                   "arithmetic": "f64", "intermediate_storage": "f32"},
-        "roofline": roof,
-        "kernels": per_kernel,
-    }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(vol, mask, ph["center"], ph["direction"])
+    line = run_plain(args, torch, st, helix, dev, args.workload)
+    if args.workload == "two_annuli" and not args.no_secondary:
+        sec = argparse.Namespace(**vars(args))
+        sec.no_cpu_baseline = True
+        sub = run_plain(sec, torch, st, helix, dev, "headline512")
+        line["headline512"] = {k: sub[k] for k in ("value", "unit", "ms_per_step", "steps")}
+        line["headline512"]["workload"] = WORKLOADS["headline512"]["desc"]
+        line["headline512"]["dominant_kernel"] = {k: sub["roofline"][k] for k in
+                                                  ("kernel", "bound", "frac", "avg_launch_ms")}
     print(json.dumps(line), flush=True)
 
 
