@@ -119,6 +119,29 @@ int st_compute(const void* volume, int dtype, const uint8_t* mask,
                void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * st_compute_noalloc -- st_compute for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It allocates nothing.
+ *
+ * Arguments, outputs and results are those of st_compute (bitwise: the same
+ * kernels and workspace layout), without workspace / workspace_bytes.  The
+ * workspace is a device array of ST_NOALLOC_SCRATCH_BYTES bytes held by the
+ * library; every device it runs on keeps its own copy until the process ends.
+ * Volumes whose st_workspace_bytes(nz, ny, nx) exceeds that size (about 128^3
+ * voxels) return ST_ERR_UNSUPPORTED before any work is enqueued.  Nothing in
+ * the array needs to start at zero.  Every call on a device shares that
+ * device's array: calls on one stream are ordered, but calls that may overlap
+ * on one device (other streams, other threads) race and give wrong results.
+ */
+#define ST_NOALLOC_SCRATCH_BYTES (128LL * 1024 * 1024)
+int st_compute_noalloc(const void* volume, int dtype, const uint8_t* mask,
+                       int64_t nz, int64_t ny, int64_t nx,
+                       double sigma, double rho, double truncate,
+                       const double* axis_center, const double* axis_direction,
+                       float* e3, float* evals, float* fa, float* ha, float* ia, uint8_t* flags,
+                       void* stream);
+
+/*
  * st_angles -- helix and intrusion angles of a given fibre field about a new
  * axis (paper: Figure 1(c), cylindrical coordinate rotation), without
  * recomputing the tensor.

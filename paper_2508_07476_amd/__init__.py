@@ -8,6 +8,7 @@ thin Python binding.  Building: ``python -m paper_2508_07476_amd.csrc.build``.
 from ._binding import (  # noqa: F401
     ALL_OUTPUTS,
     ST_BATCH_MAX_LANES,
+    ST_NOALLOC_SCRATCH_BYTES,
     ST_SURROGATE_WEIGHTS,
     SURROGATE_OUTPUTS,
     Batch,
@@ -31,6 +32,7 @@ from ._binding import (  # noqa: F401
     profile_reset,
     st_angles,
     st_compute,
+    st_compute_noalloc,
     st_filter_radius,
     st_surrogate_infer,
     st_version,

@@ -26,6 +26,7 @@ ST_FLAG_OUTSIDE_MASK = 2
 ST_FLAG_ON_AXIS = 4
 
 ST_BATCH_MAX_LANES = 8
+ST_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 
 class StChunk(ctypes.Structure):
@@ -50,6 +51,8 @@ SIGNATURES = {
     "st_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
     "st_compute": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _D, _D, _D, _DP, _DP,
                                   _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_compute_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _D, _D, _D, _DP, _DP,
+                                          _P, _P, _P, _P, _P, _P, _P]),
     "st_angles": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _DP, _DP, _P, _P, _P, _P]),
     "st_surrogate_infer": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _SZ, _D,
                                           _D, _D, _D, _DP, _DP, _P, _P, _P, _P, _P, _P]),
@@ -209,6 +212,32 @@ def st_compute(volume, sigma: float, rho: float, truncate: float = 4.0, mask=Non
                               _ptr(res.get("e3")), _ptr(res.get("evals")), _ptr(res.get("fa")),
                               _ptr(res.get("ha")), _ptr(res.get("ia")), _ptr(res.get("flags")),
                               _ptr(workspace), ws_bytes, _stream_handle(dev))
+    _check(code)
+    return res
+
+
+def st_compute_noalloc(volume, sigma: float, rho: float, truncate: float = 4.0, mask=None,
+                       axis_center=None, axis_direction=None,
+                       outputs: Iterable[str] = ("e3", "fa", "ha", "ia", "flags"),
+                       out: Optional[dict] = None):
+    """``st_compute`` with the library's own device scratch as workspace: the
+    library allocates nothing (volumes up to about 128^3; see include/st.h).
+    Outputs not supplied in ``out`` are allocated here by PyTorch."""
+    import torch
+    lib = load_library()
+    _require_device_tensor("volume", volume, (torch.uint16, torch.float32))
+    if volume.dim() != 3:
+        raise ValueError("volume must be 3-D (nz, ny, nx)")
+    nz, ny, nx = volume.shape
+    dev = volume.device
+    mask = _mask_arg(mask, (nz, ny, nx))
+    res = _outputs(outputs, out, (nz, ny, nx), dev)
+    with torch.cuda.device(dev):
+        code = lib.st_compute_noalloc(_ptr(volume), ST_DTYPE_U16 if volume.dtype == torch.uint16 else ST_DTYPE_F32,
+                                      _ptr(mask), nz, ny, nx, float(sigma), float(rho), float(truncate),
+                                      _vec3(axis_center), _vec3(axis_direction), _ptr(res.get("e3")),
+                                      _ptr(res.get("evals")), _ptr(res.get("fa")), _ptr(res.get("ha")),
+                                      _ptr(res.get("ia")), _ptr(res.get("flags")), _stream_handle(dev))
     _check(code)
     return res
 

@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libst.so")
 # (source, extra defines, object name); the strided instantiations are split into
 # groups so that the largest radii compile in parallel
 STRIDED_GROUPS = 8
-UNITS = ([("st_api.hip", [], "st_api"), ("st_batch.hip", [], "st_batch"), ("st_surrogate.hip", [], "st_surrogate"),
+UNITS = ([("st_api.hip", [], "st_api"), ("st_batch.hip", [], "st_batch"), ("st_noalloc.hip", [], "st_noalloc"), ("st_surrogate.hip", [], "st_surrogate"),
           ("k_surrogate.hip", [], "k_surrogate"), ("k_strided.hip", [], "k_strided"),
           ("k_xpass.hip", [], "k_xpass"), ("k_xgrad.hip", [], "k_xgrad"),
           ("k_xfinala.hip", [], "k_xfinala"), ("k_xfinalb.hip", [], "k_xfinalb"),
