@@ -439,9 +439,10 @@ BATCH_OUTPUTS = ("e3", "fa", "ha", "ia", "flags")
 
 
 def run_batch(args, torch, st, helix, dev):
-    """Chunk-batch workload: a batch of 8 graph-replayed chains (lanes = 0), `steps` launches
-    are timed (inputs resident).  The same chunks run one st_compute call after
-    another on one stream as the unbatched reference."""
+    """Chunk-batch workload (200 halo-padded chunks): the autotuned batch is the
+    line's value; beside it the untuned 8-chain graph, the untuned grouped
+    launches and one st_compute per chunk on one stream.  Inputs resident; the
+    four share one set of output tensors."""
     spec = helix.spec_headline_u16(shape=SHAPE)
     ph = helix.generate(spec, device=dev)
     crops = helix.batch_crops(SHAPE)
@@ -452,39 +453,54 @@ def run_batch(args, torch, st, helix, dev):
                        "rho": rho, "origin": org})
     del ph["volume"], ph["mask"]
     nvox = sum(c["volume"].numel() for c in chunks)
-    batch = st.Batch(chunks, BATCH_SIGMA, TRUNCATE, axis_center=ph["center"],
-                     axis_direction=ph["direction"], outputs=BATCH_OUTPUTS, lanes=0)
-    cfg = batch.config()  # lanes = 0: 8 chains with graph replay (autotuning is switched off)
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for _ in range(args.warmup):
-        batch.launch()
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    for _ in range(args.steps):
-        batch.launch()
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / args.steps
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    kw = dict(axis_center=ph["center"], axis_direction=ph["direction"], outputs=BATCH_OUTPUTS)
+    results = None
+    modes = {}
+    for name, lanes in (("chains8", 0), ("grouped", st.ST_BATCH_GROUPED)):
+        b = st.Batch(chunks, BATCH_SIGMA, TRUNCATE, lanes=lanes, results=results, **kw)
+        results = b.results
+        ms = timed(b.launch, args.steps)
+        modes[name] = {"ms_per_step": round(ms, 4), "value": round(nvox / ms / 1e6, 4), "unit": "Gvoxels/s",
+                       "config": b.config(), "plan": b.plan()}
+        b.close()
+        torch.cuda.empty_cache()
+    b = st.Batch(chunks, BATCH_SIGMA, TRUNCATE, lanes=0, results=results, **kw)
+    t0 = time.perf_counter()
+    cfg = b.tune(reps=2)
+    tune_s = time.perf_counter() - t0
+    ms = timed(b.launch, args.steps)
+    tiles = {}
+    for i in range(len(chunks)):
+        key = "rows%d_lanes%d" % b.tiles(i)
+        tiles[key] = tiles.get(key, 0) + 1
+    tuned = {"config": cfg, "plan": b.plan(), "tile_shapes": tiles, "tune_seconds": round(tune_s, 2)}
+    b.close()
+    torch.cuda.empty_cache()
     # unbatched reference: one st_compute per chunk, in order, on one stream
     ws = torch.empty(max(st.st_workspace_bytes(tuple(c["volume"].shape)) for c in chunks),
                      dtype=torch.uint8, device=dev)
 
     def sequential():
-        for c, r in zip(chunks, batch.results):
+        for c, r in zip(chunks, results):
             center = [ph["center"][d] - c["origin"][d] for d in range(3)]
             st.st_compute(c["volume"], BATCH_SIGMA, c["rho"], TRUNCATE, mask=c["mask"], axis_center=center,
                           axis_direction=ph["direction"], outputs=BATCH_OUTPUTS, out=r, workspace=ws)
 
-    sequential()
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    reps = max(1, args.steps // 2)
-    for _ in range(reps):
-        sequential()
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    seq_ms = ev[0].elapsed_time(ev[1]) / reps
+    seq_ms = timed(sequential, max(1, args.steps // 2))
     line = {
         "metric": METRIC, "value": round(nvox / ms / 1e6, 4), "unit": "Gvoxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -492,15 +508,15 @@ def run_batch(args, torch, st, helix, dev):
         "data": "synthetic",
         "config": {"workload": f"{len(chunks)} uint16 halo-padded chunks of the 512^3 helical phantom + "
                                "mask: interior sides U{64..384} per axis, halo 3*rho, rho in {2,3,4}, "
-                               f"sigma={BATCH_SIGMA}; outputs e3, FA, HA, IA, flags",
+                               f"sigma={BATCH_SIGMA}; outputs e3, FA, HA, IA, flags; autotuned",
                    "chunks": len(chunks), "voxels": nvox, "input": "uint16",
                    "arithmetic": "f64", "intermediate_storage": "f32"},
-        "batch_config": cfg,
+        "tuned": tuned,
+        "untuned": modes,
         "unbatched": {"ms_per_step": round(seq_ms, 4), "value": round(nvox / seq_ms / 1e6, 4),
                       "unit": "Gvoxels/s", "how": "one st_compute call per chunk on one stream"},
     }
     print(json.dumps(line), flush=True)
-    batch.close()
 
 
 def main():

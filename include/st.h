@@ -179,14 +179,28 @@ int st_angles(const float* e3, const uint8_t* mask,
  *  weights         DEVICE pointer to the float32 blob; weights_bytes >= 4 * ST_SURROGATE_WEIGHTS
  *  min_confidence  in [0, 1]: inside the mask, voxels whose confidence is below
  *                  it take st_compute's outputs (sigma, rho, truncate: as
- *                  st_compute, validated only when min_confidence > 0; the
- *                  structure-tensor path then runs on the whole volume)
+ *                  st_compute, validated only when min_confidence > 0)
  *  e3 [3][N], fa, ha, ia, confidence [N]: DEVICE outputs, each may be NULL, at
  *                  least one given; ha / ia need the axis.  Outside the mask
  *                  every output is 0.  confidence is the surrogate's.
- * Device workspace (128 bytes per voxel of activations, plus st_compute's
- * workspace and 24 bytes per voxel with a fallback) is taken with
- * hipMallocAsync on `stream` and released the same way.
+ * Fallback (min_confidence > 0 and an output other than confidence): the
+ * volume is cut into cubic tiles; a tile holding a voxel below the threshold
+ * inside the mask is flagged.  The call then waits for the flags (it is
+ * synchronous from here on) and takes the cheapest of: nothing (no tile
+ * flagged); the flagged tiles of one edge (32, 64 or 128 voxels), each
+ * gathered with the structure-tensor path's reach of context (its compiled
+ * gradient and integration radii) into a crop, all crops run as one chunk
+ * batch (st_batch_create, grouped launches where sigma allows); or the whole
+ * volume.  A crop gives its tile st_compute's whole-volume outputs bit for
+ * bit (its faces lie beyond the path's reach or on the volume's faces); ha /
+ * ia also when every axis_center coordinate minus an integer is exact in
+ * double (e.g. a multiple of 1/2 below 2^50).  st_surrogate_fallback_info
+ * reports which was taken.
+ * Device workspace: 128 bytes per voxel of activations, taken with
+ * hipMallocAsync on `stream` and released the same way; with a fallback, the
+ * crops (hipMalloc, about 75 bytes per crop voxel and their batch) or the
+ * whole-volume path (hipMallocAsync, st_compute's workspace plus 24 bytes per
+ * voxel).
  */
 #define ST_SURROGATE_WEIGHTS 111783
 int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
@@ -196,6 +210,49 @@ int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
                        const double* axis_center, const double* axis_direction,
                        float* e3, float* fa, float* ha, float* ia, float* confidence,
                        void* stream);
+
+/* What the calling thread's last st_surrogate_infer did for its fallback:
+ * mode 0 (none: no fallback asked or no tile flagged), 1 (flagged tiles of
+ * edge *tile_edge: *tiles crops of *voxels voxels in all) or 2 (the whole
+ * volume: *voxels = N).  Any output pointer may be NULL. */
+int st_surrogate_fallback_info(int* mode, int* tile_edge, int64_t* tiles, int64_t* voxels);
+
+/*
+ * Training of the surrogate's weights on the matrix cores.  The objective, per
+ * voxel with loss weight w (0 or 1), u = h[0:3] / |h[0:3]|, label direction t
+ * (unit) and label FA f:
+ *   l_dir = 1 - (u . t)^2;  l_fa = (sigmoid(h[3]) - f)^2;
+ *   l_conf = softplus(h[4]) - c h[4], c = [angle(u, t) < 2 degrees] (a target);
+ *   L = sum w (l_dir + l_fa + 0.1 l_conf) / sum w.
+ * Training stores every activation in bf16 (the fifth layer's too, which
+ * inference keeps in float32) and every gradient at a pre-activation in bf16;
+ * weights enter both passes rounded to bf16 and are kept in float32.
+ *
+ * st_surrogate_grad: L and its gradient for a stack of npatch patches of
+ * patch^3 voxels (1 <= patch <= 32), each its own volume with clamped faces.
+ *  patches         device [npatch * patch][patch][patch] of dtype
+ *  target_e3       device float[3][N] (N = npatch * patch^3), label directions (unit)
+ *  target_fa       device float[N];  weight: device uint8[N], 1 where the loss applies.
+ *                  Loss voxels must lie at least 5 voxels inside their patch
+ *                  (the network's receptive radius), so no face enters the gradient.
+ *  params          device float[ST_SURROGATE_WEIGHTS] (the weights blob)
+ *  grad            device float[ST_SURROGATE_WEIGHTS]: dL/dparams (0 for in_scale, in_offset)
+ *  stats           device float[8]: mean l_dir, l_fa, l_conf, L, sum w, weighted
+ *                  voxels within 2 degrees, mean angle (degrees), sum w
+ *  workspace       st_surrogate_grad_workspace_bytes(npatch, patch) device bytes, or
+ *                  NULL with workspace_bytes 0 (then allocated stream-ordered)
+ * st_surrogate_adam: one Adam step (bias-corrected, step >= 1) on every weight
+ * but in_scale and in_offset: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * params -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  All
+ * arrays device float[ST_SURROGATE_WEIGHTS].
+ */
+size_t st_surrogate_grad_workspace_bytes(int64_t npatch, int64_t patch);
+int st_surrogate_grad(const void* patches, int dtype, int64_t npatch, int64_t patch,
+                      const float* target_e3, const float* target_fa, const uint8_t* weight,
+                      const float* params, float* grad, float* stats,
+                      void* workspace, size_t workspace_bytes, void* stream);
+int st_surrogate_adam(float* params, const float* grad, float* adam_m, float* adam_v, int64_t step,
+                      double lr, double beta1, double beta2, double eps, void* stream);
 
 /*
  * Chunk batches (the paper's chunk-based processing with padding, Implementation
@@ -234,17 +291,28 @@ typedef struct st_batch st_batch;  /* opaque */
 
 /* Largest chain count of a batch. */
 #define ST_BATCH_MAX_LANES 8
+/* `lanes` value that selects grouped launches (see st_batch_create). */
+#define ST_BATCH_GROUPED (-1)
 
-/* Workspace bytes a batch of these chunks needs with `lanes` chains (0 = room
- * for ST_BATCH_MAX_LANES): one slot per chain, each st_workspace_bytes of the
- * largest chunk; 0 if a chunk's sizes are invalid. */
+/* Workspace bytes a batch of these chunks needs with `lanes` chains (0 or
+ * ST_BATCH_GROUPED = room for ST_BATCH_MAX_LANES): one slot per chain, each
+ * st_workspace_bytes of the largest chunk; 0 if a chunk's sizes are invalid. */
 size_t st_batch_workspace_bytes(const st_chunk* chunks, int nchunks, int lanes);
 
 /* Builds a batch.  chunks: HOST array of nchunks >= 1 descriptors (copied).
  * sigma, truncate: as in st_compute, shared by every chunk.  axis_center /
  * axis_direction: HOST (z, y, x) or both NULL (then ha / ia must be NULL).
- * lanes: 1..ST_BATCH_MAX_LANES, or 0 for ST_BATCH_MAX_LANES chains (the choice
- * autotuning made in every measured run).
+ * lanes: 1..ST_BATCH_MAX_LANES concurrent chains, 0 for ST_BATCH_MAX_LANES
+ * chains, or ST_BATCH_GROUPED for grouped launches: the chunks are packed into
+ * rounds whose workspaces fit the batch's workspace (first-fit decreasing),
+ * and each pass of a round is one kernel launch over all of the round's
+ * chunks that share its radius, taps and tile shape, reading every chunk's
+ * geometry from a device table (the batch allocates its small table buffer
+ * even with a caller workspace); ST_ERR_UNSUPPORTED if sigma's radius needs
+ * the three-pass gradient.  Grouped launches fill all of a caller workspace of
+ * one slot or more (fewer bytes, more and smaller rounds; with the sum of the
+ * chunks' st_workspace_bytes, rounded up to 256 each, one round); without one
+ * the batch allocates ST_BATCH_MAX_LANES slots.
  * workspace: device buffer of st_batch_workspace_bytes(chunks, nchunks, lanes)
  * bytes, or NULL for the batch to allocate (and free in st_batch_destroy).
  * On success *out holds the batch (owned by the caller, release with
@@ -261,9 +329,9 @@ int st_batch_launch(st_batch* batch, void* stream);
  * times): for every chunk alone, the gradient tile rows and the final-pass
  * segment lanes compiled for its radii; for the whole batch in direct
  * enqueue, the chain count (1, 2, 4, 8 up to the workspace slots) and split
- * targets (x1/4, x1, x4 around the chain count's default); finally the chosen
- * configuration replayed from one newly captured graph against direct
- * enqueue.  Keeps the fastest (best_ms in st_batch_config).  On an error the
+ * targets (x1/4, x1, x4 around the chain count's default), then the grouped
+ * launches; finally the chosen configuration replayed from one newly
+ * captured graph against direct enqueue.  Keeps the fastest (best_ms in st_batch_config).  On an error the
  * batch stays usable with direct enqueue.  reps >= 1. */
 int st_batch_tune(st_batch* batch, void* stream, int reps);
 
@@ -276,6 +344,11 @@ int st_batch_tune(st_batch* batch, void* stream, int reps);
  * time per launch of the configuration st_batch_tune chose (0 before tuning). */
 int st_batch_config(const st_batch* batch, int* lanes, int* use_graph, int64_t* grad_min_blocks,
                     int64_t* strided_min_waves, double* best_ms);
+
+/* How the batch launches: grouped (1) or chains (0); the rounds of the grouped
+ * mode (0 for chains); the kernel launches one st_batch_launch makes.  Any
+ * output pointer may be NULL. */
+int st_batch_plan(const st_batch* batch, int* grouped, int* rounds, int* kernels);
 
 /* Tile shapes of chunk `chunk` (0 <= chunk < nchunks): the rows of a gradient
  * tile and the lanes of a final-pass row segment; 0 means the library's

@@ -7,6 +7,7 @@ thin Python binding.  Building: ``python -m paper_2508_07476_amd.csrc.build``.
 
 from ._binding import (  # noqa: F401
     ALL_OUTPUTS,
+    ST_BATCH_GROUPED,
     ST_BATCH_MAX_LANES,
     ST_NOALLOC_SCRATCH_BYTES,
     ST_SURROGATE_WEIGHTS,
@@ -34,6 +35,10 @@ from ._binding import (  # noqa: F401
     st_compute,
     st_compute_noalloc,
     st_filter_radius,
+    st_surrogate_adam,
+    st_surrogate_fallback_info,
+    st_surrogate_grad,
+    st_surrogate_grad_workspace_bytes,
     st_surrogate_infer,
     st_version,
     st_workspace_bytes,

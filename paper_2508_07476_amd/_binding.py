@@ -26,6 +26,7 @@ ST_FLAG_OUTSIDE_MASK = 2
 ST_FLAG_ON_AXIS = 4
 
 ST_BATCH_MAX_LANES = 8
+ST_BATCH_GROUPED = -1
 ST_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 
@@ -56,6 +57,10 @@ SIGNATURES = {
     "st_angles": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _DP, _DP, _P, _P, _P, _P]),
     "st_surrogate_infer": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _SZ, _D,
                                           _D, _D, _D, _DP, _DP, _P, _P, _P, _P, _P, _P]),
+    "st_surrogate_grad_workspace_bytes": (_SZ, [_I64, _I64]),
+    "st_surrogate_grad": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_surrogate_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _D, _D, _D, _D, _P]),
+    "st_surrogate_fallback_info": (ctypes.c_int, [_P, _P, _P, _P]),
     "st_batch_workspace_bytes": (_SZ, [ctypes.POINTER(StChunk), ctypes.c_int, ctypes.c_int]),
     "st_batch_create": (ctypes.c_int, [ctypes.POINTER(StChunk), ctypes.c_int, _D, _D, _DP, _DP,
                                        ctypes.c_int, _P, _SZ, ctypes.POINTER(_P)]),
@@ -63,6 +68,8 @@ SIGNATURES = {
     "st_batch_tune": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "st_batch_config": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
+    "st_batch_plan": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int)]),
     "st_batch_tiles": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "st_batch_destroy": (ctypes.c_int, [_P]),
     "st_profile_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -326,6 +333,71 @@ def st_surrogate_infer(volume, weights, min_confidence: float = 0.0, sigma: floa
     return res
 
 
+def st_surrogate_grad(patches, target_e3, target_fa, weight, params, grad=None, stats=None, workspace=None):
+    """Gradient of the surrogate's training objective (see include/st.h) for a
+    stack of patches (npatch * P, P, P) uint16/float32 CUDA tensor, P <= 32.
+    target_e3 (3, npatch * P, P, P), target_fa (npatch * P, P, P) float32,
+    weight (npatch * P, P, P) uint8/bool, params float32[ST_SURROGATE_WEIGHTS].
+    Returns (grad, stats) float32 CUDA tensors (stats: 8 values)."""
+    import torch
+    lib = load_library()
+    _require_device_tensor("patches", patches, (torch.uint16, torch.float32))
+    if patches.dim() != 3 or patches.shape[1] != patches.shape[2] or patches.shape[0] % patches.shape[1]:
+        raise ValueError("patches must be a stack (npatch * P, P, P)")
+    P = patches.shape[1]
+    npatch = patches.shape[0] // P
+    shape = tuple(patches.shape)
+    dev = patches.device
+    _require_device_tensor("target_e3", target_e3, (torch.float32,), (3,) + shape)
+    _require_device_tensor("target_fa", target_fa, (torch.float32,), shape)
+    weight = _mask_arg(weight, shape)
+    _require_device_tensor("params", params, (torch.float32,), (ST_SURROGATE_WEIGHTS,))
+    if grad is None:
+        grad = torch.empty(ST_SURROGATE_WEIGHTS, dtype=torch.float32, device=dev)
+    if stats is None:
+        stats = torch.empty(8, dtype=torch.float32, device=dev)
+    _require_device_tensor("grad", grad, (torch.float32,), (ST_SURROGATE_WEIGHTS,))
+    _require_device_tensor("stats", stats, (torch.float32,), (8,))
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        _require_device_tensor("workspace", workspace, (torch.uint8,))
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    with torch.cuda.device(dev):
+        code = lib.st_surrogate_grad(_ptr(patches), ST_DTYPE_U16 if patches.dtype == torch.uint16 else ST_DTYPE_F32,
+                                     npatch, P, _ptr(target_e3), _ptr(target_fa), _ptr(weight), _ptr(params),
+                                     _ptr(grad), _ptr(stats), ws_ptr, ws_bytes, _stream_handle(dev))
+    _check(code)
+    return grad, stats
+
+
+def st_surrogate_fallback_info() -> dict:
+    """What this thread's last st_surrogate_infer did for its fallback: mode
+    0 (none), 1 (flagged tiles) or 2 (whole volume), the tile edge, the crop
+    count and the voxels the structure-tensor path ran on."""
+    mode, edge = ctypes.c_int(0), ctypes.c_int(0)
+    tiles, voxels = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load_library().st_surrogate_fallback_info(ctypes.byref(mode), ctypes.byref(edge), ctypes.byref(tiles),
+                                                     ctypes.byref(voxels)))
+    return {"mode": mode.value, "tile_edge": edge.value, "tiles": tiles.value, "voxels": voxels.value}
+
+
+def st_surrogate_grad_workspace_bytes(npatch: int, patch: int) -> int:
+    return load_library().st_surrogate_grad_workspace_bytes(int(npatch), int(patch))
+
+
+def st_surrogate_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                      eps: float = 1e-8):
+    """One Adam step on the surrogate's float32 weights (in place; see include/st.h)."""
+    import torch
+    lib = load_library()
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _require_device_tensor(name, t, (torch.float32,), (ST_SURROGATE_WEIGHTS,))
+    with torch.cuda.device(params.device):
+        code = lib.st_surrogate_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                                     float(beta2), float(eps), _stream_handle(params.device))
+    _check(code)
+
+
 def profile_enable(on: bool = True):
     _check(load_library().st_profile_enable(1 if on else 0))
 
@@ -357,14 +429,16 @@ class Batch:
     ``chunks``: sequence of dicts with ``volume`` (3-D uint16/float32 CUDA
     tensor), ``rho``, optional ``origin`` (z, y, x) of ``volume[0, 0, 0]`` in the
     axis' coordinates (default 0) and optional ``mask``.  Outputs (``outputs``
-    names) are allocated here and returned per chunk by :attr:`results`.
+    names) are allocated here, or taken from ``results`` (one dict per chunk),
+    and returned per chunk by :attr:`results`.
     ``lanes`` is the number of concurrent chains (1..ST_BATCH_MAX_LANES); 0 takes
-    ST_BATCH_MAX_LANES chains with graph replay.
+    ST_BATCH_MAX_LANES chains with graph replay; ST_BATCH_GROUPED (-1) takes
+    grouped launches (each pass one kernel over a round of chunks).
     """
 
     def __init__(self, chunks, sigma: float, truncate: float = 4.0, axis_center=None,
                  axis_direction=None, outputs: Iterable[str] = ("e3", "fa", "ha", "ia", "flags"),
-                 lanes: int = 0, workspace=None):
+                 lanes: int = 0, workspace=None, results=None):
         import torch
         lib = load_library()
         outputs = tuple(outputs)
@@ -395,8 +469,12 @@ class Batch:
             res = {}
             for k in outputs:
                 shape = (3, nz, ny, nx) if k in ("e3", "evals") else (nz, ny, nx)
-                res[k] = torch.empty(shape, dtype=torch.uint8 if k == "flags" else torch.float32,
-                                     device=dev)
+                dt = torch.uint8 if k == "flags" else torch.float32
+                if results is not None:  # caller-supplied output tensors (e.g. another batch's)
+                    _require_device_tensor(f"results[{i}][{k!r}]", results[i][k], (dt,), shape)
+                    res[k] = results[i][k]
+                else:
+                    res[k] = torch.empty(shape, dtype=dt, device=dev)
             self.results.append(res)
             self._keep += [vol, mask]
             org = c.get("origin", (0.0, 0.0, 0.0))
@@ -440,6 +518,12 @@ class Batch:
         vs direct enqueue on the real chunks (synchronises); returns :meth:`config`."""
         _check(load_library().st_batch_tune(self._handle(), _stream_handle(self.device), int(reps)))
         return self.config()
+
+    def plan(self) -> dict:
+        """{"grouped": bool, "rounds": grouped-mode rounds, "kernels": launches per batch launch}."""
+        g, r, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load_library().st_batch_plan(self._handle(), ctypes.byref(g), ctypes.byref(r), ctypes.byref(k)))
+        return {"grouped": bool(g.value), "rounds": r.value, "kernels": k.value}
 
     def tiles(self, chunk: int) -> tuple:
         """(gradient tile rows, final-pass segment lanes) of a chunk; 0 = library default."""

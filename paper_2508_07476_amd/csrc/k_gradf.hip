@@ -20,9 +20,9 @@
 namespace st {
 namespace {
 
-template <int R, typename Tin, int TY = grad_tile_rows(R)>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4 : 1)))
-void k_grad_fused(const GradFusedParams p) {
+// Block `blk` of the gradient pass over the volume described by p (taps wg, wd).
+template <int R, typename Tin, int TY>
+__device__ __forceinline__ void grad_fused_block(const GradGeo& p, const Taps& wg, const Taps& wd, int64_t blk) {
   constexpr int W = 2 * R + 1;
   constexpr int TX = kGradTX;
   constexpr int NT = TX * TY;  // threads: one per output column of the tile
@@ -31,7 +31,7 @@ void k_grad_fused(const GradFusedParams p) {
   constexpr int NYPOS = (TY * RX + NT - 1) / NT;   // y-filter positions per thread
   // The smoothing taps are symmetric about the centre (bit for bit, as built):
   // only taps 0..R are read, so R + 1 of them occupy scalar registers.
-  auto tg = [&](int k) { return p.wg.w[k <= R ? k : 2 * R - k]; };
+  auto tg = [&](int k) { return wg.w[k <= R ? k : 2 * R - k]; };
   __shared__ float raw[RY * RX];      // input plane (exact in float32)
   __shared__ double yb[2][TY * RX];   // y-filtered plane, float64
 
@@ -39,7 +39,7 @@ void k_grad_fused(const GradFusedParams p) {
   // Blocks are dealt round-robin to the 8 XCDs (each with its own L2); give each
   // XCD a contiguous run of tiles so that tiles sharing halo rows meet in one L2.
   const int64_t nblk = p.x_tiles * p.y_tiles * p.nchunks;
-  int64_t b = blockIdx.x;
+  int64_t b = blk;
   if (nblk % 8 == 0) b = (b % 8) * (nblk / 8) + b / 8;
   const int64_t xt = b % p.x_tiles;
   b /= p.x_tiles;
@@ -93,7 +93,7 @@ void k_grad_fused(const GradFusedParams p) {
         for (int k = 0; k < W; ++k) {
           const double v = raw[(row + k) * RX + col];
           g = fma(tg(k), v, g);
-          d = fma(p.wd.w[k], v, d);
+          d = fma(wd.w[k], v, d);
         }
         yb[0][s] = g;
         yb[1][s] = d;
@@ -106,7 +106,7 @@ void k_grad_fused(const GradFusedParams p) {
       const double u = yb[0][ty * RX + tx + k];
       const double w = yb[1][ty * RX + tx + k];
       ga = fma(tg(k), u, ga);
-      dc = fma(p.wd.w[k], u, dc);
+      dc = fma(wd.w[k], u, dc);
       gb = fma(tg(k), w, gb);
     }
     // materialise the three results here: otherwise the compiler sinks these
@@ -144,7 +144,7 @@ void k_grad_fused(const GradFusedParams p) {
       double gz = 0.0, gy = 0.0, gx = 0.0;
 #pragma unroll
       for (int k = 0; k < W; ++k) {
-        gz = fma(p.wd.w[k], wa[k], gz);
+        gz = fma(wd.w[k], wa[k], gz);
         gy = fma(tg(k), wb[k], gy);
         gx = fma(tg(k), wc[k], gx);
       }
@@ -157,6 +157,26 @@ void k_grad_fused(const GradFusedParams p) {
       __builtin_nontemporal_store(static_cast<float>(gx * gx), p.prod[5] + i);
     }
   }
+}
+
+template <int R, typename Tin, int TY = grad_tile_rows(R)>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4 : 1)))
+void k_grad_fused(const GradFusedParams p) {
+  grad_fused_block<R, Tin, TY>(p, p.wg, p.wd, blockIdx.x);
+}
+
+// One launch over a table of volumes.  Each entry's block range starts on a
+// multiple of 8, so the XCD-aware remap inside a volume sees its own blocks
+// dealt round-robin to the 8 XCDs as in a launch of its own.
+template <int R, typename Tin, int TY>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4 : 1)))
+void k_grad_fused_grouped(const GradFusedGroup p) {
+  const int64_t b = blockIdx.x;
+  const int e = group_entry(p.g.first, p.g.count, b);
+  const GradGeo g = p.g.geo[e];
+  const int64_t local = b - p.g.first[e];
+  if (local >= g.x_tiles * g.y_tiles * g.nchunks) return;  // alignment padding (block-uniform)
+  grad_fused_block<R, Tin, TY>(g, p.wg, p.wd, local);
 }
 
 template <typename Tin, int R>
@@ -179,9 +199,36 @@ hipError_t launch_r(const GradFusedParams& p, hipStream_t stream) {
 
 }  // namespace
 
+template <typename Tin, int R>
+hipError_t launch_grouped_r(int rows, const GradFusedGroup& p, int64_t blocks, hipStream_t stream) {
+  if (rows == grad_tile_rows(R)) {
+    hipLaunchKernelGGL((k_grad_fused_grouped<R, Tin, grad_tile_rows(R)>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kGradTX, grad_tile_rows(R)), 0, stream, p);
+    return hipGetLastError();
+  }
+  if constexpr (grad_rows_supported(R, 4) && grad_tile_rows(R) != 4) {
+    if (rows == 4) {
+      hipLaunchKernelGGL((k_grad_fused_grouped<R, Tin, 4>), dim3(static_cast<unsigned>(blocks)), dim3(kGradTX, 4), 0,
+                         stream, p);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream) {
 #define ST_CASE(r) case r: return in_dtype == ST_DTYPE_U16 ? launch_r<uint16_t, r>(p, stream) \
                                                            : launch_r<float, r>(p, stream);
+  switch (R) { ST_CASE(1) ST_CASE(2) ST_CASE(3) ST_CASE(4) ST_CASE(5) ST_CASE(6) ST_CASE(7) ST_CASE(8)
+    default: return hipErrorInvalidValue; }
+#undef ST_CASE
+}
+
+hipError_t launch_grad_fused_grouped(int R, int in_dtype, int rows, const GradFusedGroup& p, int64_t blocks,
+                                     hipStream_t stream) {
+  if (blocks < 1) return hipSuccess;
+#define ST_CASE(r) case r: return in_dtype == ST_DTYPE_U16 ? launch_grouped_r<uint16_t, r>(rows, p, blocks, stream) \
+                                                           : launch_grouped_r<float, r>(rows, p, blocks, stream);
   switch (R) { ST_CASE(1) ST_CASE(2) ST_CASE(3) ST_CASE(4) ST_CASE(5) ST_CASE(6) ST_CASE(7) ST_CASE(8)
     default: return hipErrorInvalidValue; }
 #undef ST_CASE

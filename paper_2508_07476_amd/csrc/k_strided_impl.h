@@ -20,12 +20,13 @@ namespace strided_impl {
 // SAME: the outputs have the inputs' strides (every pass but the gradient's
 // z pass over the caller's volume); one stride pair then serves both, which
 // keeps the scalar registers within budget.
+// Block `blk` of the pass over the volume described by p (taps wg, wd).
 template <int R, typename Tin, bool WITH_D, bool SAME>
-__global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
+__device__ __forceinline__ void strided_block(const StridedGeo& p, const Taps& wg, const Taps& wd, int64_t blk) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;  // 0..63, x within the tile
   // flattened block index: x tile fastest, then "other" tile, then chunk, then job
-  int64_t b = blockIdx.x;
+  int64_t b = blk;
   const int64_t xt = b % p.x_tiles;
   b /= p.x_tiles;
   const int64_t ot = b % p.o_tiles;
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
           const double u = win[(J + k) % W];
-          g = fma(p.wg.w[k <= R ? k : 2 * R - k], u, g);
-          if constexpr (WITH_D) d = fma(k <= R ? p.wd.w[k] : -p.wd.w[2 * R - k], u, d);
+          g = fma(wg.w[k <= R ? k : 2 * R - k], u, g);
+          if constexpr (WITH_D) d = fma(k <= R ? wd.w[k] : -wd.w[2 * R - k], u, d);
         }
         if (active) {
           const int64_t at = static_cast<int64_t>(a0 + t) * soa + lane;
@@ -99,6 +100,29 @@ __global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
       (step(std::integral_constant<int, J>{}), ...);
     }(std::make_integer_sequence<int, W>{});
   }
+}
+
+template <int R, typename Tin, bool WITH_D, bool SAME>
+__global__ __launch_bounds__(256) void k_strided(const StridedParams p) {
+  strided_block<R, Tin, WITH_D, SAME>(p, p.wg, p.wd, blockIdx.x);
+}
+
+// One launch over a table of volumes (integration: float32 in, smoothing taps,
+// shared strides).
+template <int R>
+__global__ __launch_bounds__(256) void k_strided_grouped(const StridedGroup p) {
+  const int64_t b = blockIdx.x;
+  const int e = group_entry(p.g.first, p.g.count, b);
+  const StridedGeo g = p.g.geo[e];
+  const int64_t local = b - p.g.first[e];
+  if (local >= g.x_tiles * g.o_tiles * g.nchunks * g.njobs) return;  // block-uniform
+  strided_block<R, float, false, true>(g, p.wg, p.wg, local);
+}
+
+template <int R>
+hipError_t launch_grouped_r(const StridedGroup& p, int64_t blocks, hipStream_t stream) {
+  hipLaunchKernelGGL((k_strided_grouped<R>), dim3(static_cast<unsigned>(blocks)), dim3(64, 4), 0, stream, p);
+  return hipGetLastError();
 }
 
 // Outputs with strides of their own are supported by the two-output variant

@@ -15,7 +15,10 @@ namespace st {
   }
 #define ST_U16(r) ST_DEFINE(u16d, uint16_t, true, r)
 #define ST_F32D(r) ST_DEFINE(f32d, float, true, r)
-#define ST_F32(r) ST_DEFINE(f32, float, false, r)
+#define ST_F32(r) ST_DEFINE(f32, float, false, r) \
+  hipError_t strided_grouped_##r(const StridedGroup& p, int64_t blocks, hipStream_t stream) { \
+    return strided_impl::launch_grouped_r<r>(p, blocks, stream);                               \
+  }
 
 #if ST_STRIDED_GROUP == 0
 ST_RADII_SIGMA(ST_U16)

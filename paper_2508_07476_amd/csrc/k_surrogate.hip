@@ -54,8 +54,11 @@ __global__ void k_sg_pack(const float* blob, __bf16* w1, __bf16* w25) {
   }
 }
 
-// FIRST: input is the raw volume (one channel); LAST: the epilogue is the head.
-template <bool FIRST, bool LAST, typename Tin>
+// FIRST: input is the raw volume (one channel); LAST: the epilogue is the head;
+// BWD (training, backward data pass): no bias, and the output is multiplied by
+// the ReLU mask of p.prev (the forward activation at the output voxel) instead
+// of passing through ReLU.
+template <bool FIRST, bool LAST, typename Tin, bool BWD = false>
 __global__ __launch_bounds__(NT) void k_sg_conv(const SgConvParams p) {
   constexpr int WN = FIRST ? C * 32 : 27 * C * C;             // bf16 weights staged
   constexpr int AN = FIRST ? 3 * PLANE_VOX : 3 * PLANE_VOX * C;  // bf16 activations staged
@@ -200,8 +203,15 @@ __global__ __launch_bounds__(NT) void k_sg_conv(const SgConvParams p) {
           for (int m = 0; m < 2; ++m) {
             const int co = 16 * m + 4 * lk;
             bf16x4 o;
+            if constexpr (BWD) {
+              const bf16x4 xm = *reinterpret_cast<const bf16x4*>(p.prev + vox * C + co);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) o[r] = static_cast<__bf16>(fmaxf(acc[m][n][r] + bias[co + r], 0.f));
+              for (int r = 0; r < 4; ++r)
+                o[r] = static_cast<__bf16>(static_cast<float>(xm[r]) > 0.f ? acc[m][n][r] : 0.f);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) o[r] = static_cast<__bf16>(fmaxf(acc[m][n][r] + bias[co + r], 0.f));
+            }
             *reinterpret_cast<bf16x4*>(p.out + vox * C + co) = o;
           }
         }
@@ -281,14 +291,14 @@ __global__ void k_sg_merge(const SgMergeParams p) {
   if (p.ia) p.ia[i] = p.pia[i];
 }
 
-template <bool FIRST, bool LAST>
+template <bool FIRST, bool LAST, bool BWD = false>
 hipError_t launch_conv(const SgConvParams& p, int dtype, hipStream_t stream) {
   const int64_t blocks = p.x_tiles * p.y_tiles * ((p.nz + p.zchunk - 1) / p.zchunk);
   if (dtype == ST_DTYPE_U16)
-    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, uint16_t>), dim3(static_cast<unsigned>(blocks)), dim3(NT), 0,
+    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, uint16_t, BWD>), dim3(static_cast<unsigned>(blocks)), dim3(NT), 0,
                        stream, p);
   else
-    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, float>), dim3(static_cast<unsigned>(blocks)), dim3(NT), 0,
+    hipLaunchKernelGGL((k_sg_conv<FIRST, LAST, float, BWD>), dim3(static_cast<unsigned>(blocks)), dim3(NT), 0,
                        stream, p);
   return hipGetLastError();
 }
@@ -305,6 +315,14 @@ hipError_t launch_sg_conv(int layer, int dtype, const SgConvParams& p, hipStream
   if (layer == 1) return launch_conv<true, false>(p, dtype, stream);
   if (layer == kSgLayers) return launch_conv<false, true>(p, ST_DTYPE_F32, stream);
   return launch_conv<false, false>(p, ST_DTYPE_F32, stream);
+}
+
+hipError_t launch_sg_conv_hidden(bool first, int dtype, const SgConvParams& p, hipStream_t stream) {
+  return first ? launch_conv<true, false>(p, dtype, stream) : launch_conv<false, false>(p, ST_DTYPE_F32, stream);
+}
+
+hipError_t launch_sg_conv_bwd(const SgConvParams& p, hipStream_t stream) {
+  return launch_conv<false, false, true>(p, ST_DTYPE_F32, stream);
 }
 
 hipError_t launch_sg_merge(const SgMergeParams& p, hipStream_t stream) {

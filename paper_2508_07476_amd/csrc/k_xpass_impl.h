@@ -144,18 +144,19 @@ __global__ __launch_bounds__(64) void k_xgrad(const XGradParams p) {
 // segment of 256 outputs, or four of 64 for rows whose width would leave much
 // of a 256-wide segment idle.  Results are parked in the staged rows (free once
 // every window has been read) and leave as 16-byte stores.
+// Block `blk` of the final pass over the volume described by p (taps w); lds
+// holds the block's staged rows.
 template <int R, int TL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TL == 16 ? 4 : 1)))
-void k_xfinal(const XFinalParams p) {
+__device__ __forceinline__ void xfinal_block(const XFinalGeo& p, const Taps& w, int64_t blk,
+                                             float (&lds)[6][(64 / TL) * lds_row(R, TL)]) {
   constexpr int LR = lds_row(R, TL);
-  constexpr int RPW = 64 / TL;  // rows per wave
-  __shared__ __attribute__((aligned(16))) float lds[6][RPW * LR];
   const int lane = threadIdx.x;
   // row segment of the lane and lane within it (0 and lane for one segment per
   // wave, which keeps the row wave-uniform)
   const int sub = TL == 64 ? 0 : lane / TL, l = TL == 64 ? lane : lane % TL;
-  const int64_t xt = blockIdx.x % p.x_tiles;
-  const int64_t row0 = (blockIdx.x / p.x_tiles) * RPW;  // first row of the wave
+  constexpr int RPW = 64 / TL;  // rows per wave
+  const int64_t xt = blk % p.x_tiles;
+  const int64_t row0 = (blk / p.x_tiles) * RPW;  // first row of the wave
   const int64_t row = row0 + sub;
   const bool row_ok = row < p.nrows;
   const int64_t rr = row_ok ? row : p.nrows - 1;  // loads of a missing row stay in range
@@ -188,7 +189,7 @@ void k_xfinal(const XFinalParams p) {
 
   double acc[6][kXVec];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) conv4<R, true>(seg[c], l, p.w, acc[c]);
+  for (int c = 0; c < 6; ++c) conv4<R, true>(seg[c], l, w, acc[c]);
   __syncthreads();  // every window read before the rows receive results
 
   // (z, y) of the lane's row; with several rows per wave the wave's first row
@@ -305,6 +306,26 @@ void k_xfinal(const XFinalParams p) {
   if (p.ia) store4(p.ia + base, x, nxi, vec_row, o4[5]);
 }
 
+template <int R, int TL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TL == 16 ? 4 : 1)))
+void k_xfinal(const XFinalParams p) {
+  __shared__ __attribute__((aligned(16))) float lds[6][(64 / TL) * lds_row(R, TL)];
+  xfinal_block<R, TL>(p, p.w, blockIdx.x, lds);
+}
+
+// One launch over a table of volumes that share the taps and the segment width.
+template <int R, int TL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TL == 16 ? 4 : 1)))
+void k_xfinal_grouped(const XFinalGroup p) {
+  __shared__ __attribute__((aligned(16))) float lds[6][(64 / TL) * lds_row(R, TL)];
+  const int64_t b = blockIdx.x;
+  const int e = group_entry(p.g.first, p.g.count, b);
+  const XFinalGeo g = p.g.geo[e];
+  const int64_t local = b - p.g.first[e];
+  if (local >= g.x_tiles * (TL == 64 ? g.nrows : (g.nrows + 3) / 4)) return;  // block-uniform
+  xfinal_block<R, TL>(g, p.w, local, lds);
+}
+
 template <int R>
 hipError_t launch_xgrad_r(const XGradParams& p, hipStream_t stream) {
   const int64_t blocks = p.x_tiles * p.nrows;
@@ -325,6 +346,21 @@ hipError_t launch_xfinal_r(const XFinalParams& p, hipStream_t stream) {
     if (p.tile_lanes == 16) {
       const int64_t blocks = p.x_tiles * ((p.nrows + 3) / 4);
       hipLaunchKernelGGL((k_xfinal<R, 16>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int R>
+hipError_t launch_xfinal_grouped_r(int lanes, const XFinalGroup& p, int64_t blocks, hipStream_t stream) {
+  if (lanes == 64) {
+    hipLaunchKernelGGL((k_xfinal_grouped<R, 64>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
+    return hipGetLastError();
+  }
+  if constexpr (R <= kXNarrowMaxRadius) {
+    if (lanes == 16) {
+      hipLaunchKernelGGL((k_xfinal_grouped<R, 16>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, stream, p);
       return hipGetLastError();
     }
   }

@@ -220,6 +220,13 @@ hipError_t timed_call(const char* name, hipStream_t stream, const std::function<
   return ::timed(name, stream, fn);
 }
 
+int path_halo(double sigma, double rho, double truncate) {
+  const int rs = radius_of(sigma, truncate), rr = radius_of(rho, truncate);
+  if (rs < 0 || rr < 0) return -1;
+  const int ps = padded_radius(rs, true), pr = padded_radius(rr, false);
+  return (ps > 0 ? ps : rs) + (pr > 0 ? pr : rr);
+}
+
 size_t path_workspace_bytes(int64_t nz, int64_t ny, int64_t nx) {
   if (nz < 1 || ny < 1 || nx < 1) return 0;
   int64_t m;
@@ -293,19 +300,9 @@ int check_path_buffers(const PathArgs& a) {
   return ST_OK;
 }
 
-hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const LaunchShape& shape,
-                        bool profile, const char** stage_out) {
+void plan_path(const PathArgs& a, char* ws, const LaunchShape& shape, PathPlan* plan) {
   const void* volume = a.volume;
-  const int dtype = a.dtype;
-  const uint8_t* mask = a.mask;
-  const int64_t nz = a.nz, ny = a.ny, nx = a.nx, n = a.n;
-  float* e3 = a.e3; float* evals = a.evals; float* fa = a.fa; float* ha = a.ha; float* ia = a.ia;
-  uint8_t* flags = a.flags;
-  const bool has_axis = a.has_axis;
-  const int rs = radius_of(a.sigma, a.truncate), rr = radius_of(a.rho, a.truncate);
-  auto timed = [&](const char* name, hipStream_t s, auto&& fn) -> hipError_t {
-    return profile ? ::timed(name, s, fn) : fn();
-  };
+  const int64_t nz = a.nz, ny = a.ny, nx = a.nx;
   // workspace planes: rows of `pitch` elements (the volume's rows are nx long)
   const int64_t pitch = ws_pitch(nx);
   const size_t pb = plane_bytes(nz * ny * pitch);
@@ -317,16 +314,18 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
   }
 
   // compiled radii: the next one up, taps zero-padded
+  const int rs = radius_of(a.sigma, a.truncate), rr = radius_of(a.rho, a.truncate);
   const int ps = st::padded_radius(rs, true), pr = st::padded_radius(rr, false);
+  plan->rs = ps;
+  plan->rr = pr;
   st::Taps gs, ds, gr;
   make_taps(a.sigma, rs, ps, gs, &ds);
   make_taps(a.rho, rr, pr, gr, nullptr);
 
   // in_volume: the jobs read the caller's volume (rows of nx), else workspace
   // planes; outputs are always workspace planes
-  auto strided = [&](bool zaxis, bool in_volume, int njobs, const st::StridedJob* jobs, int R,
-                     int in_dtype, bool with_d, const st::Taps& wg, const st::Taps* wd) {
-    st::StridedParams p;
+  auto strided = [&](st::StridedParams& p, bool zaxis, bool in_volume, int njobs, const st::StridedJob* jobs,
+                     int R, const st::Taps& wg, const st::Taps* wd) {
     std::memset(&p, 0, sizeof(p));
     for (int j = 0; j < njobs; ++j) p.job[j] = jobs[j];
     p.njobs = njobs;
@@ -353,112 +352,115 @@ hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const L
     p.nchunks = static_cast<int>((p.n_axis + p.chunk - 1) / p.chunk);
     p.wg = wg;
     if (wd) p.wd = *wd;
-    return st::launch_strided(R, in_dtype, with_d, p, stream);
   };
 
+  // gradient at sigma and outer product: one fused pass when the radius and the
+  // plane size allow it, else z pass (G, D), y pass, x pass + outer product
+  plan->fused_grad = ps <= st::kGradMaxRadius && ny * nx <= INT32_MAX;
+  if (plan->fused_grad) {
+    st::GradFusedParams& p = plan->grad;
+    std::memset(&p, 0, sizeof(p));
+    p.vol = volume;
+    for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
+    p.nz = nz; p.ny = ny; p.nx = nx;
+    p.opitch = pitch;
+    p.x_tiles = (nx + st::kGradTX - 1) / st::kGradTX;
+    const int64_t rows = shape.grad_rows ? shape.grad_rows : st::grad_tile_rows(ps);
+    p.rows = static_cast<int>(rows);
+    p.y_tiles = (ny + rows - 1) / rows;
+    // split z until there are enough waves to fill the chip (grad_min_blocks
+    // counts blocks of four waves), keeping chunks >= 8R
+    const int64_t waves_per_block = rows;  // one wave per tile row
+    int64_t nch = 1;
+    while (p.x_tiles * p.y_tiles * nch * waves_per_block < 4 * shape.grad_min_blocks && nz / (2 * nch) >= 8 * ps)
+      nch *= 2;
+    p.chunk = (nz + nch - 1) / nch;
+    p.nchunks = static_cast<int>((nz + p.chunk - 1) / p.chunk);
+    p.wg = gs; p.wd = ds;
+  } else {
+    const st::StridedJob jz = {volume, B[0], B[1]}, jy0 = {B[0], A[0], A[1]}, jy1 = {B[1], A[2], nullptr};
+    strided(plan->grad_z, true, true, 1, &jz, ps, gs, &ds);
+    strided(plan->grad_y0, false, false, 1, &jy0, ps, gs, &ds);
+    strided(plan->grad_y1, false, false, 1, &jy1, ps, gs, nullptr);
+    st::XGradParams& p = plan->grad_x;
+    std::memset(&p, 0, sizeof(p));
+    p.gg = A[0]; p.dg = A[1]; p.gd = A[2];
+    for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
+    p.nx = nx; p.pitch = pitch; p.nrows = nz * ny; p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
+    p.vec_ok = 1;  // workspace rows: 16-byte aligned
+    p.wg = gs; p.wd = ds;
+  }
+  // integration: z pass, y pass (6 components each)
+  st::StridedJob j[6];
+  for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{B[c], A[c], nullptr};
+  strided(plan->int_z, true, false, 6, j, pr, gr, nullptr);
+  for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{A[c], B[c], nullptr};
+  strided(plan->int_y, false, false, 6, j, pr, gr, nullptr);
+  // x integration fused with eigen, FA, angles
+  st::XFinalParams& p = plan->fin;
+  std::memset(&p, 0, sizeof(p));
+  for (int c = 0; c < 6; ++c) p.s[c] = B[c];
+  p.mask = a.mask; p.e3 = a.e3; p.evals = a.evals; p.fa = a.fa; p.ha = a.ha; p.ia = a.ia; p.flags = a.flags;
+  p.n = a.n; p.nz = nz; p.ny = ny; p.nx = nx; p.pitch = pitch; p.nrows = nz * ny;
+  // segments of 64 lanes (256 outputs), or of 16 (64 outputs, four rows per
+  // wave) where that fills at least 5 % more of the lanes
+  auto fill = [&](int64_t tl) {
+    const int64_t t = tl * st::kXVec;
+    return static_cast<double>(nx) / static_cast<double>(t * ((nx + t - 1) / t));
+  };
+  p.tile_lanes = shape.xfinal_lanes ? shape.xfinal_lanes
+                                    : (pr <= st::kXNarrowMaxRadius && fill(16) >= fill(64) + 0.05) ? 16 : 64;
+  p.x_tiles = (nx + p.tile_lanes * st::kXVec - 1) / (p.tile_lanes * st::kXVec);
+  bool vec = true;  // the kernel also checks each row's and plane's offset
+  for (const void* q : {static_cast<const void*>(a.e3), static_cast<const void*>(a.evals),
+                        static_cast<const void*>(a.fa), static_cast<const void*>(a.ha),
+                        static_cast<const void*>(a.ia)})
+    if (q && (reinterpret_cast<uintptr_t>(q) % 16) != 0) vec = false;
+  if (a.flags && (reinterpret_cast<uintptr_t>(a.flags) % 4) != 0) vec = false;
+  p.vec_ok = vec;
+  p.has_axis = a.has_axis;
+  if (a.has_axis)
+    for (int i = 0; i < 3; ++i) { p.center[i] = a.center[i]; p.dir[i] = a.unit[i]; }
+  p.w = gr;
+}
+
+hipError_t enqueue_path(const PathArgs& a, char* ws, hipStream_t stream, const LaunchShape& shape,
+                        bool profile, const char** stage_out) {
+  auto timed = [&](const char* name, hipStream_t s, auto&& fn) -> hipError_t {
+    return profile ? ::timed(name, s, fn) : fn();
+  };
+  PathPlan pl;
+  plan_path(a, ws, shape, &pl);
+  const int ps = pl.rs, pr = pl.rr;
   hipError_t e = hipSuccess;
   const char* stage = "";
   do {
-    // gradient at sigma and outer product: one fused pass when the radius and the
-    // plane size allow it, else z pass (G, D), y pass, x pass + outer product
-    const bool fused_grad = ps <= st::kGradMaxRadius && ny * nx <= INT32_MAX;
-    if (fused_grad) {
-      st::GradFusedParams p;
-      std::memset(&p, 0, sizeof(p));
-      p.vol = volume;
-      for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
-      p.nz = nz; p.ny = ny; p.nx = nx;
-      p.opitch = pitch;
-      p.x_tiles = (nx + st::kGradTX - 1) / st::kGradTX;
-      const int64_t rows = shape.grad_rows ? shape.grad_rows : st::grad_tile_rows(ps);
-      p.rows = static_cast<int>(rows);
-      p.y_tiles = (ny + rows - 1) / rows;
-      // split z until there are enough waves to fill the chip (grad_min_blocks
-      // counts blocks of four waves), keeping chunks >= 8R
-      const int64_t waves_per_block = rows;  // one wave per tile row
-      int64_t nch = 1;
-      while (p.x_tiles * p.y_tiles * nch * waves_per_block < 4 * shape.grad_min_blocks && nz / (2 * nch) >= 8 * ps)
-        nch *= 2;
-      p.chunk = (nz + nch - 1) / nch;
-      p.nchunks = static_cast<int>((nz + p.chunk - 1) / p.chunk);
-      p.wg = gs; p.wd = ds;
+    if (pl.fused_grad) {
       stage = "grad_fused";
-      e = timed("grad_fused", stream, [&] { return st::launch_grad_fused(ps, dtype, p, stream); });
+      e = timed("grad_fused", stream, [&] { return st::launch_grad_fused(ps, a.dtype, pl.grad, stream); });
       if (e != hipSuccess) break;
     } else {
-    {
-      st::StridedJob j = {volume, B[0], B[1]};
       stage = "grad_z";
-      e = timed("grad_z", stream, [&] { return strided(true, true, 1, &j, ps, dtype, true, gs, &ds); });
+      e = timed("grad_z", stream, [&] { return st::launch_strided(ps, a.dtype, true, pl.grad_z, stream); });
       if (e != hipSuccess) break;
-    }
-    {
-      st::StridedJob j0 = {B[0], A[0], A[1]};
       stage = "grad_y";
-      e = timed("grad_y", stream, [&] { return strided(false, false, 1, &j0, ps, ST_DTYPE_F32, true, gs, &ds); });
+      e = timed("grad_y", stream, [&] { return st::launch_strided(ps, ST_DTYPE_F32, true, pl.grad_y0, stream); });
       if (e != hipSuccess) break;
-      st::StridedJob j1 = {B[1], A[2], nullptr};
-      e = timed("grad_y", stream, [&] { return strided(false, false, 1, &j1, ps, ST_DTYPE_F32, false, gs, nullptr); });
+      e = timed("grad_y", stream, [&] { return st::launch_strided(ps, ST_DTYPE_F32, false, pl.grad_y1, stream); });
       if (e != hipSuccess) break;
-    }
-    {
-      st::XGradParams p;
-      std::memset(&p, 0, sizeof(p));
-      p.gg = A[0]; p.dg = A[1]; p.gd = A[2];
-      for (int c = 0; c < 6; ++c) p.prod[c] = B[c];
-      p.nx = nx; p.pitch = pitch; p.nrows = nz * ny; p.x_tiles = (nx + st::kXTile - 1) / st::kXTile;
-      p.vec_ok = 1;  // workspace rows: 16-byte aligned
-      p.wg = gs; p.wd = ds;
       stage = "grad_x_outer";
-      e = timed("grad_x_outer", stream, [&] { return st::launch_xgrad(ps, p, stream); });
+      e = timed("grad_x_outer", stream, [&] { return st::launch_xgrad(ps, pl.grad_x, stream); });
       if (e != hipSuccess) break;
     }
-    }
-    // integration: z pass, y pass (6 components each)
-    {
-      st::StridedJob j[6];
-      for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{B[c], A[c], nullptr};
-      stage = "integrate_z";
-      e = timed("integrate_z", stream, [&] { return strided(true, false, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
-      if (e != hipSuccess) break;
-      for (int c = 0; c < 6; ++c) j[c] = st::StridedJob{A[c], B[c], nullptr};
-      stage = "integrate_y";
-      e = timed("integrate_y", stream, [&] { return strided(false, false, 6, j, pr, ST_DTYPE_F32, false, gr, nullptr); });
-      if (e != hipSuccess) break;
-    }
-    // x integration fused with eigen, FA, angles
-    {
-      st::XFinalParams p;
-      std::memset(&p, 0, sizeof(p));
-      for (int c = 0; c < 6; ++c) p.s[c] = B[c];
-      p.mask = mask; p.e3 = e3; p.evals = evals; p.fa = fa; p.ha = ha; p.ia = ia; p.flags = flags;
-      p.n = n; p.nz = nz; p.ny = ny; p.nx = nx; p.pitch = pitch; p.nrows = nz * ny;
-      // segments of 64 lanes (256 outputs), or of 16 (64 outputs, four rows per
-      // wave) where that fills at least 5 % more of the lanes
-      auto fill = [&](int64_t tl) {
-        const int64_t t = tl * st::kXVec;
-        return static_cast<double>(nx) / static_cast<double>(t * ((nx + t - 1) / t));
-      };
-      p.tile_lanes = shape.xfinal_lanes ? shape.xfinal_lanes
-                                        : (pr <= st::kXNarrowMaxRadius && fill(16) >= fill(64) + 0.05) ? 16 : 64;
-      p.x_tiles = (nx + p.tile_lanes * st::kXVec - 1) / (p.tile_lanes * st::kXVec);
-      bool vec = true;  // the kernel also checks each row's and plane's offset
-      for (const void* q : {static_cast<const void*>(e3), static_cast<const void*>(evals),
-                            static_cast<const void*>(fa), static_cast<const void*>(ha),
-                            static_cast<const void*>(ia)})
-        if (q && (reinterpret_cast<uintptr_t>(q) % 16) != 0) vec = false;
-      if (flags && (reinterpret_cast<uintptr_t>(flags) % 4) != 0) vec = false;
-      p.vec_ok = vec;
-      p.has_axis = has_axis;
-      if (has_axis)
-        for (int i = 0; i < 3; ++i) { p.center[i] = a.center[i]; p.dir[i] = a.unit[i]; }
-      p.w = gr;
-      stage = "integrate_x_eigen";
-      e = timed("integrate_x_eigen", stream, [&] { return st::launch_xfinal(pr, p, stream); });
-      if (e != hipSuccess) break;
-    }
+    stage = "integrate_z";
+    e = timed("integrate_z", stream, [&] { return st::launch_strided(pr, ST_DTYPE_F32, false, pl.int_z, stream); });
+    if (e != hipSuccess) break;
+    stage = "integrate_y";
+    e = timed("integrate_y", stream, [&] { return st::launch_strided(pr, ST_DTYPE_F32, false, pl.int_y, stream); });
+    if (e != hipSuccess) break;
+    stage = "integrate_x_eigen";
+    e = timed("integrate_x_eigen", stream, [&] { return st::launch_xfinal(pr, pl.fin, stream); });
   } while (false);
-
   *stage_out = stage;
   return e;
 }

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -49,6 +50,20 @@ struct ForkJoin {
   const hipEvent_t* join;
 };
 
+// One launch of the grouped mode: a pass over every chunk of a round that
+// shares its radius, taps and tile shape; its tables live in the batch's table
+// buffer.
+struct GroupLaunch {
+  int kind = 0;    // 0 gradient, 1 z integration, 2 y integration, 3 final pass
+  int R = 0;       // compiled radius
+  int shape = 0;   // gradient tile rows, or final-pass segment lanes
+  int dtype = 0;   // input type (gradient)
+  st::Taps w0{}, w1{};  // gradient: smoothing, derivative taps; integration: smoothing taps
+  size_t geo = 0, first = 0;  // byte offsets of the entry table and the block table
+  int count = 0;
+  int64_t blocks = 0;
+};
+
 }  // namespace
 
 struct st_batch {
@@ -56,6 +71,7 @@ struct st_batch {
   std::vector<st::host::LaunchShape> tiles;  // per chunk: tile shapes (split targets unused)
   size_t slot_bytes = 0;  // workspace of the largest chunk
   int slots = 0;          // workspace slots (the largest chain count possible)
+  size_t ws_bytes = 0;    // workspace bytes the grouped rounds may fill
   char* ws = nullptr;
   bool owned = false;
   int device = 0;
@@ -73,6 +89,12 @@ struct st_batch {
   bool launched = false;
   Captured* captured = nullptr;
   std::vector<std::vector<int>> plan;  // chunk indices of every chain, in launch order
+  // grouped mode: rounds of chunks whose workspaces fit together, each pass of a
+  // round one launch per (radius, taps, tile shape) over a device table
+  bool grouped = false;
+  int rounds = 0;
+  std::vector<GroupLaunch> glaunch;
+  char* tables = nullptr;  // device buffer of the entry and block tables (owned)
 };
 
 namespace {
@@ -112,6 +134,181 @@ st::host::LaunchShape chunk_shape(const st_batch* b, int i) {
   s.grad_rows = b->tiles[i].grad_rows;
   s.xfinal_lanes = b->tiles[i].xfinal_lanes;
   return s;
+}
+
+// ---- grouped mode -------------------------------------------------------------
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool same_taps(const st::Taps& a, const st::Taps& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+// Plans the grouped mode for the current tile shapes and uploads its tables
+// (synchronous; the batch must be idle).  Chunks go into rounds by first-fit
+// decreasing on their workspace bytes within the batch's workspace; each chunk
+// of a round gets its own workspace region and a share of the split targets
+// in proportion to its voxels, so a round's launch splits as far as one
+// volume of the round's size would.  ST_ERR_UNSUPPORTED if a chunk needs the
+// three-pass gradient (sigma radius above the fused pass's).
+int plan_grouped(st_batch* b) {
+  const int n = static_cast<int>(b->chunks.size());
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return b->chunks[i].n > b->chunks[j].n; });
+  const size_t budget = b->ws_bytes;
+  struct Round {
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> chunk_off;
+    int64_t voxels = 0;
+  };
+  std::vector<Round> rounds;
+  for (int i : order) {
+    const st::host::PathArgs& a = b->chunks[i];
+    const size_t w = align_up(st::host::path_workspace_bytes(a.nz, a.ny, a.nx), 256);
+    size_t r = 0;
+    while (r < rounds.size() && rounds[r].used + w > budget) ++r;
+    if (r == rounds.size()) rounds.emplace_back();
+    rounds[r].chunk_off.emplace_back(i, rounds[r].used);
+    rounds[r].used += w;
+    rounds[r].voxels += a.n;
+  }
+  // launches and their tables (host copies)
+  std::vector<GroupLaunch> launches;
+  std::vector<std::vector<char>> geos;
+  std::vector<std::vector<int64_t>> firsts;
+  const st::host::LaunchShape base;
+  for (const Round& rd : rounds) {
+    std::vector<st::host::PathPlan> plans(rd.chunk_off.size());
+    for (size_t k = 0; k < rd.chunk_off.size(); ++k) {
+      const int i = rd.chunk_off[k].first;
+      st::host::LaunchShape sh = chunk_shape(b, i);
+      const double share = static_cast<double>(b->chunks[i].n) / static_cast<double>(rd.voxels);
+      sh.grad_min_blocks = std::max<int64_t>(1, static_cast<int64_t>(base.grad_min_blocks * share));
+      sh.strided_min_waves = std::max<int64_t>(1, static_cast<int64_t>(base.strided_min_waves * share));
+      st::host::plan_path(b->chunks[i], b->ws + rd.chunk_off[k].second, sh, &plans[k]);
+      if (!plans[k].fused_grad)
+        return fail(ST_ERR_UNSUPPORTED, "grouped launches need the fused gradient pass (chunk %d)", i);
+    }
+    // one pass kind at a time, entries grouped by (radius, taps, tile shape, type)
+    for (int kind = 0; kind < 4; ++kind) {
+      std::vector<bool> done(plans.size(), false);
+      for (size_t k0 = 0; k0 < plans.size(); ++k0) {
+        if (done[k0]) continue;
+        const st::host::PathPlan& p0 = plans[k0];
+        GroupLaunch L;
+        L.kind = kind;
+        if (kind == 0) {
+          L.R = p0.rs; L.shape = p0.grad.rows; L.dtype = b->chunks[rd.chunk_off[k0].first].dtype;
+          L.w0 = p0.grad.wg; L.w1 = p0.grad.wd;
+        } else if (kind < 3) {
+          L.R = p0.rr; L.w0 = kind == 1 ? p0.int_z.wg : p0.int_y.wg;
+        } else {
+          L.R = p0.rr; L.shape = p0.fin.tile_lanes; L.w0 = p0.fin.w;
+        }
+        std::vector<char> geo;
+        std::vector<int64_t> first{0};
+        for (size_t k = k0; k < plans.size(); ++k) {
+          if (done[k]) continue;
+          const st::host::PathPlan& p = plans[k];
+          int64_t nb = 0;
+          const char* g = nullptr;
+          size_t gsz = 0;
+          if (kind == 0) {
+            if (p.rs != L.R || p.grad.rows != L.shape || b->chunks[rd.chunk_off[k].first].dtype != L.dtype ||
+                !same_taps(p.grad.wg, L.w0) || !same_taps(p.grad.wd, L.w1))
+              continue;
+            nb = align_up(static_cast<size_t>(st::grad_blocks(p.grad)), 8);  // XCD remap per volume
+            g = reinterpret_cast<const char*>(static_cast<const st::GradGeo*>(&p.grad));
+            gsz = sizeof(st::GradGeo);
+          } else if (kind < 3) {
+            const st::StridedParams& q = kind == 1 ? p.int_z : p.int_y;
+            if (p.rr != L.R || !same_taps(q.wg, L.w0)) continue;
+            nb = st::strided_blocks(q);
+            g = reinterpret_cast<const char*>(static_cast<const st::StridedGeo*>(&q));
+            gsz = sizeof(st::StridedGeo);
+          } else {
+            if (p.rr != L.R || p.fin.tile_lanes != L.shape || !same_taps(p.fin.w, L.w0)) continue;
+            nb = st::xfinal_blocks(p.fin);
+            g = reinterpret_cast<const char*>(static_cast<const st::XFinalGeo*>(&p.fin));
+            gsz = sizeof(st::XFinalGeo);
+          }
+          done[k] = true;
+          geo.insert(geo.end(), g, g + gsz);
+          first.push_back(first.back() + nb);
+        }
+        L.count = static_cast<int>(first.size()) - 1;
+        L.blocks = first.back();
+        if (L.blocks > INT32_MAX)
+          return fail(ST_ERR_UNSUPPORTED, "a grouped launch of %lld blocks exceeds the grid limit", (long long)L.blocks);
+        launches.push_back(L);
+        geos.push_back(std::move(geo));
+        firsts.push_back(std::move(first));
+      }
+    }
+  }
+  // one device buffer for every table, each 256-byte aligned
+  size_t total = 0;
+  for (size_t l = 0; l < launches.size(); ++l) {
+    launches[l].geo = total;
+    total = align_up(total + geos[l].size(), 256);
+    launches[l].first = total;
+    total = align_up(total + firsts[l].size() * sizeof(int64_t), 256);
+  }
+  std::vector<char> host(total, 0);
+  for (size_t l = 0; l < launches.size(); ++l) {
+    std::memcpy(host.data() + launches[l].geo, geos[l].data(), geos[l].size());
+    std::memcpy(host.data() + launches[l].first, firsts[l].data(), firsts[l].size() * sizeof(int64_t));
+  }
+  if (b->tables) {
+    (void)hipFree(b->tables);
+    b->tables = nullptr;
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->tables), std::max<size_t>(total, 256));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b->tables = nullptr;
+    return e == hipErrorOutOfMemory ? fail(ST_ERR_OUT_OF_MEMORY, "batch table allocation failed")
+                                    : device_fail(e, "hipMalloc (batch tables)");
+  }
+  e = hipMemcpy(b->tables, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(e, "hipMemcpy (batch tables)");
+  b->glaunch = std::move(launches);
+  b->rounds = static_cast<int>(rounds.size());
+  return ST_OK;
+}
+
+// Enqueues the grouped launches on `stream`, round after round.
+hipError_t enqueue_grouped(st_batch* b, hipStream_t stream, const char** stage) {
+  for (const GroupLaunch& L : b->glaunch) {
+    hipError_t e;
+    if (L.kind == 0) {
+      st::GradFusedGroup g;
+      g.g.geo = reinterpret_cast<const st::GradGeo*>(b->tables + L.geo);
+      g.g.first = reinterpret_cast<const int64_t*>(b->tables + L.first);
+      g.g.count = L.count;
+      g.wg = L.w0;
+      g.wd = L.w1;
+      *stage = "grad_fused (grouped)";
+      e = st::launch_grad_fused_grouped(L.R, L.dtype, L.shape, g, L.blocks, stream);
+    } else if (L.kind < 3) {
+      st::StridedGroup g;
+      g.g.geo = reinterpret_cast<const st::StridedGeo*>(b->tables + L.geo);
+      g.g.first = reinterpret_cast<const int64_t*>(b->tables + L.first);
+      g.g.count = L.count;
+      g.wg = L.w0;
+      *stage = L.kind == 1 ? "integrate_z (grouped)" : "integrate_y (grouped)";
+      e = st::launch_strided_grouped(L.R, g, L.blocks, stream);
+    } else {
+      st::XFinalGroup g;
+      g.g.geo = reinterpret_cast<const st::XFinalGeo*>(b->tables + L.geo);
+      g.g.first = reinterpret_cast<const int64_t*>(b->tables + L.first);
+      g.g.count = L.count;
+      g.w = L.w0;
+      *stage = "integrate_x_eigen (grouped)";
+      e = st::launch_xfinal_grouped(L.R, L.shape, g, L.blocks, stream);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Fork from `root` into the chains, enqueue every chunk, join back into `root`.
@@ -178,7 +375,8 @@ int capture(st_batch* b) {
     return device_fail(e, "hipStreamBeginCapture");
   }
   const char* stage = "";
-  hipError_t ee = enqueue_all(b, b->cap, ForkJoin{c->fork, c->join}, &stage);
+  hipError_t ee = b->grouped ? enqueue_grouped(b, b->cap, &stage)
+                             : enqueue_all(b, b->cap, ForkJoin{c->fork, c->join}, &stage);
   e = hipStreamEndCapture(b->cap, &c->graph);  // always ends the capture, also after a failure
   if (ee != hipSuccess || e != hipSuccess) {
     destroy_captured(c);
@@ -203,6 +401,8 @@ int launch(st_batch* b, hipStream_t stream) {
   stage = "hipGraphLaunch";
   if (b->use_graph) {
     e = hipGraphLaunch(b->captured->exec, stream);
+  } else if (b->grouped) {
+    e = enqueue_grouped(b, stream, &stage);
   } else {
     e = enqueue_all(b, stream, ForkJoin{b->dfork, b->djoin}, &stage);
   }
@@ -226,6 +426,7 @@ void release(st_batch* b) {
   if (b->dfork) (void)hipEventDestroy(b->dfork);
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->owned && b->ws) (void)hipFree(b->ws);
+  if (b->tables) (void)hipFree(b->tables);
   delete b;
 }
 
@@ -283,10 +484,10 @@ void tile_candidates(const st::host::PathArgs& a, std::vector<int>* rows, std::v
 extern "C" {
 
 size_t st_batch_workspace_bytes(const st_chunk* chunks, int nchunks, int lanes) {
-  if (chunks == nullptr || nchunks < 1 || lanes < 0 || lanes > ST_BATCH_MAX_LANES) return 0;
+  if (chunks == nullptr || nchunks < 1 || lanes < ST_BATCH_GROUPED || lanes > ST_BATCH_MAX_LANES) return 0;
   size_t slot = 0;
   if (!slot_plan(chunks, nchunks, &slot)) return 0;
-  const size_t slots = lanes == 0 ? ST_BATCH_MAX_LANES : static_cast<size_t>(lanes);
+  const size_t slots = lanes <= 0 ? ST_BATCH_MAX_LANES : static_cast<size_t>(lanes);
   size_t total = 0;
   if (__builtin_mul_overflow(slot, slots, &total)) return 0;
   return total;
@@ -300,8 +501,8 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   if (out == nullptr) return fail(ST_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (chunks == nullptr || nchunks < 1) return fail(ST_ERR_INVALID_ARG, "need at least one chunk");
-  if (lanes < 0 || lanes > ST_BATCH_MAX_LANES)
-    return fail(ST_ERR_INVALID_ARG, "lanes %d is outside 0..%d", lanes, ST_BATCH_MAX_LANES);
+  if (lanes < ST_BATCH_GROUPED || lanes > ST_BATCH_MAX_LANES)
+    return fail(ST_ERR_INVALID_ARG, "lanes %d is outside %d..%d", lanes, ST_BATCH_GROUPED, ST_BATCH_MAX_LANES);
   if ((axis_center == nullptr) != (axis_direction == nullptr))
     return fail(ST_ERR_INVALID_ARG, "axis_center and axis_direction must both be given or both be NULL");
   std::vector<st::host::PathArgs> args(nchunks);
@@ -322,8 +523,13 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   }
   size_t slot = 0;
   if (!slot_plan(chunks, nchunks, &slot)) return fail(ST_ERR_INVALID_ARG, "chunk sizes out of range");
-  const int slots = lanes == 0 ? ST_BATCH_MAX_LANES : lanes;
+  // chains need one slot each; grouped launches need one slot and use all the
+  // workspace they are given (less workspace, more rounds; more, fewer)
+  int slots = lanes <= 0 ? ST_BATCH_MAX_LANES : lanes;
+  if (lanes == ST_BATCH_GROUPED && workspace != nullptr && workspace_bytes >= slot)
+    slots = static_cast<int>(std::min<size_t>(ST_BATCH_MAX_LANES, workspace_bytes / slot));
   const size_t need = slot * static_cast<size_t>(slots);
+  const size_t ws_bytes = lanes == ST_BATCH_GROUPED && workspace != nullptr ? workspace_bytes : need;
   if (workspace == nullptr && workspace_bytes != 0)
     return fail(ST_ERR_INVALID_ARG, "workspace is NULL but workspace_bytes is %zu", workspace_bytes);
   if (workspace != nullptr && workspace_bytes < need)
@@ -338,7 +544,7 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
     if (st != ST_OK) return fail(st, "chunk %d: %s", i, st_last_error());
   }
   if (workspace != nullptr) {
-    int st = st::host::check_device_buffer(workspace, need, "workspace");
+    int st = st::host::check_device_buffer(workspace, ws_bytes, "workspace");
     if (st != ST_OK) return st;
   }
 
@@ -348,7 +554,9 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
   b->tiles.assign(b->chunks.size(), st::host::LaunchShape{});
   b->slot_bytes = slot;
   b->slots = slots;
-  b->lanes = lanes == 0 ? slots : lanes;
+  b->ws_bytes = ws_bytes;
+  b->lanes = lanes <= 0 ? slots : lanes;
+  b->grouped = lanes == ST_BATCH_GROUPED;
   if (b->lanes > 1) {
     // concurrent chains fill the chip together: split each chunk's passes a
     // quarter as far as a lone volume would be (fewer z halo planes)
@@ -383,7 +591,8 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
     return e == hipErrorOutOfMemory ? fail(ST_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e))
                                     : device_fail(e, what);
   }
-  int st = capture(b);
+  int st = b->grouped ? plan_grouped(b) : ST_OK;
+  if (st == ST_OK) st = capture(b);
   if (st != ST_OK) {
     release(b);
     return st;
@@ -447,8 +656,10 @@ int st_batch_tune(st_batch* b, void* stream_, int reps) {
     }
   }
 
-  // 2. chain count, then split targets: the whole batch, direct enqueue
+  // 2. chain count, then split targets: the whole batch, direct enqueue; then
+  // the grouped launches (when every chunk has the fused gradient pass)
   const st::host::LaunchShape base;
+  b->grouped = false;
   auto time_batch = [&](int nl, double factor, double* ms) -> int {
     b->lanes = nl;
     b->shape.grad_min_blocks = std::max<int64_t>(1, static_cast<int64_t>(base.grad_min_blocks * factor));
@@ -473,10 +684,32 @@ int st_batch_tune(st_batch* b, void* stream_, int reps) {
     if (st == ST_OK && ms < best_ms) { best_ms = ms; best_factor = f; }
   }
 
+  bool best_grouped = false;
+  if (st == ST_OK) {
+    b->grouped = true;
+    double ms = 0.0;
+    int gst = plan_grouped(b);
+    if (gst == ST_OK) gst = time_reps(stream, t0, t1, reps, [&] { return launch(b, stream); }, &ms);
+    if (gst == ST_OK && ms < best_ms) {
+      best_ms = ms;
+      best_grouped = true;
+    } else if (gst != ST_OK && gst != ST_ERR_UNSUPPORTED) {
+      st = gst;
+    }
+    b->grouped = false;
+    st::host::clear_error();
+  }
+
   // 3. the chosen configuration replayed from one graph, against direct enqueue
   if (st == ST_OK) {
     double direct_ms = 0.0, graph_ms = 0.0;
-    st = time_batch(best_lanes, best_factor, &direct_ms);
+    if (best_grouped) {
+      b->grouped = true;
+      b->lanes = 1;
+      st = time_reps(stream, t0, t1, reps, [&] { return launch(b, stream); }, &direct_ms);
+    } else {
+      st = time_batch(best_lanes, best_factor, &direct_ms);
+    }
     if (st == ST_OK) st = capture(b);
     if (st == ST_OK) {
       b->use_graph = true;
@@ -495,10 +728,11 @@ int st_batch_tune(st_batch* b, void* stream_, int reps) {
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (st != ST_OK) {
-    // leave a usable batch: direct enqueue of whatever configuration was set
+    // leave a usable batch: direct enqueue of the chains with whatever configuration was set
     (void)wait_idle(b);
     drop_graph(b);
     b->use_graph = false;
+    b->grouped = false;
     make_plan(b);
   }
   return st;
@@ -513,6 +747,27 @@ int st_batch_config(const st_batch* b, int* lanes, int* use_graph, int64_t* grad
   if (grad_min_blocks) *grad_min_blocks = b->shape.grad_min_blocks;
   if (strided_min_waves) *strided_min_waves = b->shape.strided_min_waves;
   if (best_ms) *best_ms = b->best_ms;
+  return ST_OK;
+}
+
+int st_batch_plan(const st_batch* b, int* grouped, int* rounds, int* kernels) {
+  st::host::clear_error();
+  if (b == nullptr) return fail(ST_ERR_INVALID_ARG, "batch is NULL");
+  if (grouped) *grouped = b->grouped ? 1 : 0;
+  if (rounds) *rounds = b->grouped ? b->rounds : 0;
+  if (kernels) {
+    int64_t k = 0;
+    if (b->grouped) {
+      k = static_cast<int64_t>(b->glaunch.size());
+    } else {
+      for (const st::host::PathArgs& a : b->chunks) {
+        st::host::PathPlan pl;
+        st::host::plan_path(a, b->ws, st::host::LaunchShape{}, &pl);
+        k += pl.fused_grad ? 4 : 7;
+      }
+    }
+    *kernels = static_cast<int>(k);
+  }
   return ST_OK;
 }
 

@@ -21,6 +21,17 @@ __device__ __forceinline__ int reflect_lane(int m, int n) {
   return m < n ? m : p - 1 - m;
 }
 
+// Entry of a grouped launch that block b belongs to: the last e with
+// first[e] <= b (b is wave-uniform, so the search runs on the scalar unit).
+__device__ __forceinline__ int group_entry(const int64_t* __restrict__ first, int count, int64_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ float load_as_float(const uint16_t* p) { return static_cast<float>(*p); }
 __device__ __forceinline__ float load_as_float(const float* p) { return *p; }
 

@@ -93,6 +93,25 @@ inline int64_t ws_pitch(int64_t nx) { return nx > 32 ? (nx + 31) / 32 * 32 : (nx
 // is out of range.
 size_t path_workspace_bytes(int64_t nz, int64_t ny, int64_t nx);
 
+// Reach of the pass sequence: an output depends on the input voxels within
+// this Chebyshev distance (the gradient's and the integration's compiled
+// radii), so a crop whose faces lie this far from a voxel, or on the volume's
+// own faces, gives that voxel's outputs bit for bit; -1 for invalid scales.
+int path_halo(double sigma, double rho, double truncate);
+
+// The launches of the pass sequence of `a` with workspace `ws`: compiled radii,
+// taps and geometry, exactly as enqueue_path launches them.
+struct PathPlan {
+  int rs, rr;                       // compiled gradient and integration radii
+  bool fused_grad;                  // one fused gradient pass (else grad_z, grad_y0, grad_y1, grad_x)
+  GradFusedParams grad;
+  StridedParams grad_z, grad_y0, grad_y1;
+  XGradParams grad_x;
+  StridedParams int_z, int_y;       // integration along z and y
+  XFinalParams fin;                 // x integration, eigen-decomposition, FA, angles
+};
+void plan_path(const PathArgs& a, char* ws, const LaunchShape& shape, PathPlan* plan);
+
 // Enqueues the pass sequence of `a` on `stream` with workspace `ws`.  With
 // `profile`, each launch is bracketed by the library's timing events (when
 // profiling is enabled).  On failure returns the HIP error and names the pass

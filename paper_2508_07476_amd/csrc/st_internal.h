@@ -50,7 +50,8 @@ struct StridedJob {
   float* out_d;
 };
 
-struct StridedParams {
+// Geometry of one strided launch (per volume in a grouped launch).
+struct StridedGeo {
   StridedJob job[6];
   int njobs;
   int nchunks;       // chunks along the filtered axis
@@ -64,6 +65,9 @@ struct StridedParams {
   int64_t nx;
   int64_t x_tiles;   // ceil(nx / 64)
   int64_t o_tiles;   // ceil(n_other / 4)
+};
+
+struct StridedParams : StridedGeo {
   Taps wg;           // smoothing taps: symmetric about the centre (read as such)
   Taps wd;           // derivative taps: antisymmetric about the centre
 };
@@ -88,7 +92,7 @@ struct XGradParams {
 };
 
 // ---- x-axis integration fused with eigen-decomposition, FA and angles ------
-struct XFinalParams {
+struct XFinalGeo {
   const float* s[6];  // z- and y-integrated products, (zz, zy, zx, yy, yx, xx)
   const uint8_t* mask;
   float* e3;          // [3][N] or null
@@ -108,6 +112,9 @@ struct XFinalParams {
   int has_axis;
   double center[3];   // (z, y, x)
   double dir[3];      // unit (z, y, x)
+};
+
+struct XFinalParams : XFinalGeo {
   Taps w;
 };
 
@@ -128,7 +135,7 @@ hipError_t launch_xfinal(int R, const XFinalParams& p, hipStream_t stream);
 // chunk of z; each input plane of the chunk (plus z halo) is staged in LDS,
 // filtered along y and then x, and the three partial results of each column
 // enter register windows that are filtered along z.
-struct GradFusedParams {
+struct GradGeo {
   const void* vol;
   float* prod[6];     // zz, zy, zx, yy, yx, xx
   int64_t nz, ny, nx;
@@ -137,6 +144,9 @@ struct GradFusedParams {
   int64_t chunk;      // z outputs per block
   int nchunks;
   int rows;           // output rows (y) per block, one wave each: grad_rows_supported(R, rows)
+};
+
+struct GradFusedParams : GradGeo {
   Taps wg;
   Taps wd;
 };
@@ -150,6 +160,48 @@ constexpr bool grad_rows_supported(int R, int rows) {
 }
 constexpr int kGradMaxRadius = 8;  // larger sigma radii use the three separate passes
 hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream);
+
+// ---- grouped launches: one launch over several volumes ---------------------
+// Block b of a grouped launch works on table entry e with
+// first[e] <= b < first[e + 1], as block b - first[e] of that volume alone
+// (blocks past that volume's own grid return at once).  Every entry of one
+// launch shares the taps, the radius and the tile shape.  The tables are
+// device memory owned by the caller of the launch.
+template <class Geo>
+struct Grouped {
+  const Geo* geo;        // [count]
+  const int64_t* first;  // [count + 1], first[0] = 0, nondecreasing
+  int count;
+};
+
+struct GradFusedGroup {
+  Grouped<GradGeo> g;
+  Taps wg;
+  Taps wd;
+};
+struct StridedGroup {      // integration passes: float32 input, smoothing taps only
+  Grouped<StridedGeo> g;
+  Taps wg;
+};
+struct XFinalGroup {
+  Grouped<XFinalGeo> g;
+  Taps w;
+};
+
+// Blocks of one volume alone in each pass (what the entry's range must hold).
+inline int64_t grad_blocks(const GradGeo& g) { return g.x_tiles * g.y_tiles * g.nchunks; }
+inline int64_t strided_blocks(const StridedGeo& g) { return g.x_tiles * g.o_tiles * g.nchunks * g.njobs; }
+inline int64_t xfinal_blocks(const XFinalGeo& g) {
+  return g.x_tiles * (g.tile_lanes == 64 ? g.nrows : (g.nrows + 3) / 4);
+}
+
+// `blocks` = first[count] of the host copy of the table.  rows / lanes: the tile
+// shape every entry uses.  Strided entries must have njobs = 6 and share input
+// and output strides (SAME).
+hipError_t launch_grad_fused_grouped(int R, int in_dtype, int rows, const GradFusedGroup& p, int64_t blocks,
+                                     hipStream_t stream);
+hipError_t launch_strided_grouped(int R, const StridedGroup& p, int64_t blocks, hipStream_t stream);
+hipError_t launch_xfinal_grouped(int R, int lanes, const XFinalGroup& p, int64_t blocks, hipStream_t stream);
 
 // ---- standalone angles ------------------------------------------------------
 struct AnglesParams {

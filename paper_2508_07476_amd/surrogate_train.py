@@ -1,26 +1,32 @@
-"""Offline training of the orientation surrogate's weights (not part of any
-inference path: st_surrogate_infer evaluates the network in HIP kernels).
+"""Training of the orientation surrogate's weights on the library's own
+kernels: every forward and backward pass is st_surrogate_grad (bf16 MFMA
+convolutions, float32 accumulation and master weights) and every update is
+st_surrogate_adam.  This module only builds the data: labelled phantoms, the
+patch set, the held-out evaluation.
 
 The network is the one st_surrogate_infer evaluates (include/st.h): five 3x3x3
 convolutions with 32 channels, ReLU and clamped faces, then a 1x1x1 head with
-five outputs (fibre vector, FA logit, confidence logit).  Training uses
-PyTorch autograd in float32 on synthetic rod-lattice phantoms whose helix range,
-rod period and noise are drawn per volume (helix angles of +-[30, 80] degrees
-across the wall, period 3..8 voxels, noise 0.01..0.2); half the volumes hold a
-whole, strongly curved annulus, half a piece of a wide wall (radii 60..290)
-whose axis lies outside the volume.  Labels are the outputs
-of the structure-tensor path, st_compute (sigma, rho as given), on the same
-volumes:
+five outputs (fibre vector, FA logit, confidence logit).  The objective
+(include/st.h, st_surrogate_grad) is
 
-  loss = mean(1 - (u . t)^2)                 (sign-invariant direction, u = h[0:3]/|h[0:3]|)
-       + mean((sigmoid(h[3]) - FA_t)^2)
-       + 0.1 * BCE(h[4], [angle(u, t) < 2 deg])   (confidence: "within 2 degrees")
+  mean(1 - (u . t)^2) + mean((sigmoid(h3) - FA_t)^2) + 0.1 BCE(h4, [angle(u, t) < 2 deg])
 
-over masked, non-degenerate voxels at least 5 voxels inside each training patch.
-The result is written as the float32 blob the C ABI takes, with a JSON record of
-the settings.
+over the weighted voxels, u = h[0:3] / |h[0:3]|, t the label's unit vector.
 
-Usage (on a GPU machine):  python -m paper_2508_07476_amd.surrogate_train out.npy [--steps N]
+Data: rod-lattice helical phantoms whose helix range, rod period and noise are
+drawn per volume (helix angles of +-[30, 80] degrees across the wall, period
+3..8 voxels, noise 0.01..0.2); half hold a whole, strongly curved annulus, half
+a piece of a wide wall whose axis lies outside the volume.  Labels are
+st_compute's e3 and FA at (sigma, rho) on the same volumes; voxels outside the
+mask, degenerate voxels and voxels within the network's receptive radius of a
+patch face carry weight 0.  The patch set is a fixed list of `--patches`
+origins (32^3 patches holding at least `--min-weight` weighted voxels) visited
+in a fresh order every epoch.  Held-out phantoms, drawn from other seeds, give
+the reported angle error of st_surrogate_infer against st_compute and the
+fallback fraction at the confidence threshold.
+
+Usage (on a GPU machine):
+  python -m paper_2508_07476_amd.surrogate_train out.npy [--patches 100000] [--epochs E]
 """
 
 from __future__ import annotations
@@ -36,103 +42,160 @@ import numpy as np
 IN_SCALE = 4.0 / 65535.0
 IN_OFFSET = -2.0
 MARGIN = 5  # receptive radius of the network
+CHANNELS = 32
 
 
-def build_model(torch):
-    nn = torch.nn
-    layers = []
-    cin = 1
-    for _ in range(5):
-        layers += [nn.Conv3d(cin, 32, 3, padding=1, padding_mode="replicate"), nn.ReLU()]
-        cin = 32
-    layers.append(nn.Conv3d(32, 5, 1))
-    return nn.Sequential(*layers)
-
-
-def export_blob(model) -> np.ndarray:
-    """Flatten the model into the st_surrogate_infer weights layout."""
-    convs = [m for m in model if m.__class__.__name__ == "Conv3d"]
+def init_blob(rng) -> np.ndarray:
+    """He-normal convolution weights, zero biases, small head: the blob layout
+    of st_surrogate_infer (in_scale, in_offset, then per layer W[co][ci][27], b[co],
+    then the head W[5][32], b[5])."""
     parts = [np.array([IN_SCALE, IN_OFFSET])]
-    for c in convs[:5]:
-        w = c.weight.detach().cpu().numpy()  # (co, ci, 3, 3, 3): tap 9 kz + 3 ky + kx
-        parts += [w.reshape(w.shape[0], w.shape[1], 27).ravel(), c.bias.detach().cpu().numpy()]
-    h = convs[5]
-    parts += [h.weight.detach().cpu().numpy().reshape(5, 32).ravel(), h.bias.detach().cpu().numpy()]
+    for layer in range(5):
+        cin = 1 if layer == 0 else CHANNELS
+        parts.append(rng.normal(scale=math.sqrt(2.0 / (27 * cin)), size=CHANNELS * cin * 27))
+        parts.append(np.zeros(CHANNELS))
+    parts.append(rng.normal(scale=math.sqrt(1.0 / CHANNELS), size=5 * CHANNELS))
+    parts.append(np.zeros(5))
     return np.concatenate(parts).astype(np.float32)
 
 
+def phantom_spec(helix, rng, shape, seed):
+    a_in = float(rng.uniform(30, 80))
+    a_out = -float(rng.uniform(30, 80))
+    if rng.random() < 0.5:
+        a_in, a_out = a_out, a_in
+    centre = None
+    if seed % 2 == 0:  # a whole, strongly curved annulus inside the volume
+        r_out = min(shape[1], shape[2]) / 2 - 2
+        r_in = float(rng.uniform(0.15, 0.4)) * r_out
+    else:  # a piece of a wide, weakly curved wall: the axis lies outside the volume
+        r_in = float(rng.uniform(60.0, 160.0))
+        r_out = r_in + float(rng.uniform(60.0, 130.0))
+        r_mid, th = 0.5 * (r_in + r_out), float(rng.uniform(0, 2 * np.pi))
+        c = [(s - 1) / 2.0 for s in shape]
+        centre = (c[0], c[1] - r_mid * np.sin(th), c[2] - r_mid * np.cos(th))
+    return helix.PhantomSpec(shape=shape, annuli=(helix.Annulus(r_in, r_out, a_in, a_out),),
+                             period=float(rng.uniform(3.0, 8.0)), noise=(float(rng.uniform(0.01, 0.2)),),
+                             dtype="u16", seed=int(rng.integers(1 << 30)), with_mask=True, center=centre)
+
+
 def make_pool(torch, st, helix, n, shape, sigma, rho, seed, dev):
-    """n labelled volumes: (volume, target e3, target FA, weight mask)."""
+    """n labelled volumes stacked: volume (n, S, S, S) (uint16 bytes held as int16), e3 (3, n, S, S, S),
+    FA (n, S, S, S), weight (n, S, S, S) u8 (inside the mask, not degenerate)."""
     rng = np.random.default_rng(seed)
-    pool = []
+    vols = torch.empty((n,) + shape, dtype=torch.int16, device=dev)  # uint16 bytes
+    e3 = torch.empty((3, n) + shape, dtype=torch.float32, device=dev)
+    fa = torch.empty((n,) + shape, dtype=torch.float32, device=dev)
+    good = torch.empty((n,) + shape, dtype=torch.uint8, device=dev)
+    specs = []
     for i in range(n):
-        a_in = float(rng.uniform(30, 80))
-        a_out = -float(rng.uniform(30, 80))
-        if rng.random() < 0.5:
-            a_in, a_out = a_out, a_in
-        centre = None
-        if i % 2 == 0:  # a whole, strongly curved annulus inside the volume
-            r_out = min(shape[1], shape[2]) / 2 - 2
-            r_in = float(rng.uniform(0.15, 0.4)) * r_out
-        else:  # a piece of a wide, weakly curved wall: the axis lies outside the volume
-            r_in = float(rng.uniform(60.0, 160.0))
-            r_out = r_in + float(rng.uniform(60.0, 130.0))
-            r_mid, th = 0.5 * (r_in + r_out), float(rng.uniform(0, 2 * np.pi))
-            c = [(n - 1) / 2.0 for n in shape]
-            centre = (c[0], c[1] - r_mid * np.sin(th), c[2] - r_mid * np.cos(th))
-        spec = helix.PhantomSpec(shape=shape, annuli=(helix.Annulus(r_in, r_out, a_in, a_out),),
-                                 period=float(rng.uniform(3.0, 8.0)), noise=(float(rng.uniform(0.01, 0.2)),),
-                                 dtype="u16", seed=int(rng.integers(1 << 30)), with_mask=True, center=centre)
+        spec = phantom_spec(helix, rng, shape, seed * 1000 + i)
         ph = helix.generate(spec, device=dev)
         lab = st.st_compute(ph["volume"], sigma, rho, mask=ph["mask"], outputs=("e3", "fa", "flags"))
-        good = (lab["flags"] == 0).float()  # inside the mask and not degenerate
-        pool.append((ph["volume"], lab["e3"], lab["fa"], good))
+        vols[i] = ph["volume"].view(torch.int16)
+        e3[:, i] = lab["e3"]
+        fa[i] = lab["fa"]
+        good[i] = (lab["flags"] == 0).to(torch.uint8)
+        specs.append(spec)
     torch.cuda.synchronize()
-    return pool
+    return {"vol": vols, "e3": e3, "fa": fa, "good": good, "specs": specs}
 
 
-def sample(torch, pool, rng, batch, p):
-    xs, ts, fs, ws = [], [], [], []
-    for _ in range(batch):
-        vol, e3, fa, good = pool[rng.integers(len(pool))]
-        nz, ny, nx = vol.shape
-        z, y, x = (int(rng.integers(0, s - p + 1)) for s in (nz, ny, nx))
-        sl = (slice(z, z + p), slice(y, y + p), slice(x, x + p))
-        xs.append(vol[sl].float() * IN_SCALE + IN_OFFSET)
-        ts.append(e3[(slice(None),) + sl])
-        fs.append(fa[sl])
-        w = good[sl].clone()
-        w[:MARGIN] = 0; w[-MARGIN:] = 0
-        w[:, :MARGIN] = 0; w[:, -MARGIN:] = 0
-        w[:, :, :MARGIN] = 0; w[:, :, -MARGIN:] = 0
-        ws.append(w)
-    return (torch.stack(xs)[:, None], torch.stack(ts), torch.stack(fs), torch.stack(ws))
+def patch_origins(torch, pool, count, P, min_weight, seed):
+    """`count` patch origins (volume, z, y, x) whose weighted interior holds at
+    least min_weight voxels, drawn uniformly with a fixed seed."""
+    n, S = pool["vol"].shape[0], pool["vol"].shape[1]
+    # integral image of the weight: the interior [o + MARGIN, o + P - MARGIN) per axis
+    c = torch.nn.functional.pad(pool["good"].to(torch.int32), (1, 0, 1, 0, 1, 0))
+    c = c.cumsum(1).cumsum(2).cumsum(3)
+    lim = S - P + 1
+    a, b = MARGIN, MARGIN + lim
+    e, f = P - MARGIN, P - MARGIN + lim
+    box = (c[:, e:f, e:f, e:f] - c[:, a:b, e:f, e:f] - c[:, e:f, a:b, e:f] - c[:, e:f, e:f, a:b]
+           + c[:, a:b, a:b, e:f] + c[:, a:b, e:f, a:b] + c[:, e:f, a:b, a:b] - c[:, a:b, a:b, a:b])
+    box_cpu = box.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        cand = rng.integers(0, [n, lim, lim, lim], size=(4 * count, 4))
+        ok = box_cpu[cand[:, 0], cand[:, 1], cand[:, 2], cand[:, 3]] >= min_weight
+        out.extend(cand[ok].tolist())
+    return np.asarray(out[:count], dtype=np.int64)
 
 
-def losses(torch, h, t, fa_t, w):
-    u = h[:, :3]
-    u = u / (u.norm(dim=1, keepdim=True) + 1e-12)
-    dot = (u * t).sum(1)
-    wsum = w.sum().clamp_min(1.0)
-    l_dir = ((1 - dot * dot) * w).sum() / wsum
-    l_fa = ((torch.sigmoid(h[:, 3]) - fa_t) ** 2 * w).sum() / wsum
-    ang = torch.acos(dot.abs().clamp(max=1.0)).detach()
-    good = (ang < math.radians(2.0)).float()
-    l_conf = (torch.nn.functional.binary_cross_entropy_with_logits(h[:, 4], good, reduction="none") * w).sum() / wsum
-    return l_dir, l_fa, l_conf, ang
+class Gatherer:
+    """Patch stacks gathered from the pool with one indexing kernel per tensor."""
+
+    def __init__(self, torch, pool, P, batch, dev):
+        self.t, self.pool, self.P = torch, pool, P
+        S = pool["vol"].shape[1]
+        r = torch.arange(P, device=dev)
+        self.off = ((r[:, None, None] * S + r[None, :, None]) * S + r[None, None, :]).reshape(1, -1)
+        m = torch.zeros((P, P, P), dtype=torch.uint8, device=dev)
+        m[MARGIN:P - MARGIN, MARGIN:P - MARGIN, MARGIN:P - MARGIN] = 1
+        self.margin = m.reshape(1, -1)
+        self.S, self.n = S, pool["vol"].shape[0]
+        self.flat = {k: pool[k].reshape(-1) for k in ("vol", "fa", "good")}
+        self.e3 = pool["e3"].reshape(3, -1)
+
+    def __call__(self, origins):
+        t, P, S = self.t, self.P, self.S
+        o = t.as_tensor(origins, device=self.off.device)
+        base = ((o[:, 0] * S + o[:, 1]) * S + o[:, 2]) * S + o[:, 3]
+        idx = (base[:, None] + self.off).reshape(-1)
+        B = o.shape[0]
+        shape = (B * P, P, P)
+        vol = self.flat["vol"][idx].reshape(shape).view(t.uint16)
+        fa = self.flat["fa"][idx].reshape(shape)
+        w = (self.flat["good"][idx].reshape(B, -1) * self.margin).reshape(shape)
+        e3 = self.e3[:, idx].reshape((3,) + shape)
+        return vol, e3, fa, w
+
+
+def evaluate(torch, st, helix, blob, count, shape, sigma, rho, seed, dev, thresholds=(0.9,)):
+    """Angle error of st_surrogate_infer against st_compute (unit vectors up to
+    sign) on held-out phantoms, over voxels inside the mask and not degenerate;
+    for each threshold the fraction of those voxels below it (the fallback
+    fraction) and the error of the rest."""
+    rng = np.random.default_rng(seed)
+    angs, confs = [], []
+    for i in range(count):
+        spec = phantom_spec(helix, rng, shape, seed * 1000 + i)
+        ph = helix.generate(spec, device=dev)
+        lab = st.st_compute(ph["volume"], sigma, rho, mask=ph["mask"], outputs=("e3", "flags"))
+        out = st.st_surrogate_infer(ph["volume"], blob, 0.0, sigma, rho, mask=ph["mask"],
+                                    outputs=("e3", "confidence"))
+        sel = lab["flags"] == 0
+        dot = (out["e3"] * lab["e3"]).sum(0).abs().clamp(max=1.0)
+        angs.append(torch.rad2deg(torch.acos(dot[sel])).float().cpu())
+        confs.append(out["confidence"][sel].float().cpu())
+    ang, conf = torch.cat(angs).numpy(), torch.cat(confs).numpy()
+    res = {"voxels": int(ang.size), "median_deg": float(np.median(ang)), "p90_deg": float(np.quantile(ang, 0.9)),
+           "within_2deg": float((ang < 2.0).mean())}
+    for thr in thresholds:
+        keep = conf >= thr
+        res[f"fallback_{thr}"] = float(1.0 - keep.mean())
+        res[f"median_deg_conf_{thr}"] = float(np.median(ang[keep])) if keep.any() else float("nan")
+    return res
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--patches", type=int, default=100_000)
+    ap.add_argument("--epochs", type=float, default=4.0)
+    ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--patch", type=int, default=32)
-    ap.add_argument("--volumes", type=int, default=24)
-    ap.add_argument("--shape", type=int, default=96)
-    ap.add_argument("--sigma", type=float, default=1.5)
-    ap.add_argument("--rho", type=float, default=4.0)
+    ap.add_argument("--volumes", type=int, default=48)
+    ap.add_argument("--shape", type=int, default=128)
+    ap.add_argument("--sigma", type=float, default=1.0)
+    ap.add_argument("--rho", type=float, default=2.0)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--min-weight", type=int, default=2000)
+    ap.add_argument("--eval-volumes", type=int, default=4)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--init", default=None, help="start from this blob (.npy) instead of a fresh one")
     args = ap.parse_args(argv)
 
     import torch
@@ -141,35 +204,55 @@ def main(argv=None):
     from phantom import helix
 
     dev = torch.device("cuda:0")
-    torch.manual_seed(args.seed)
     t0 = time.time()
     shape = (args.shape,) * 3
     pool = make_pool(torch, st, helix, args.volumes, shape, args.sigma, args.rho, args.seed, dev)
-    print(f"pool of {len(pool)} labelled {shape} volumes in {time.time() - t0:.1f} s", flush=True)
-    model = build_model(torch).to(dev)
-    opt = torch.optim.Adam(model.parameters(), lr=1e-3)
-    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, args.steps)
-    rng = np.random.default_rng(args.seed + 1)
-    for step in range(1, args.steps + 1):
-        x, t, fa_t, w = sample(torch, pool, rng, args.batch, args.patch)
-        h = model(x)
-        l_dir, l_fa, l_conf, ang = losses(torch, h, t, fa_t, w)
-        loss = l_dir + l_fa + 0.1 * l_conf
-        opt.zero_grad(set_to_none=True)
-        loss.backward()
-        opt.step()
-        sched.step()
-        if step % 250 == 0 or step == 1:
-            m = w > 0
-            med = float(torch.quantile(ang[m][:200000], 0.5)) if m.any() else float("nan")
-            print(f"step {step}: loss {float(loss.detach()):.4f} dir {float(l_dir):.4f} fa {float(l_fa):.5f} "
-                  f"conf {float(l_conf):.4f} median angle {math.degrees(med):.2f} deg "
-                  f"({time.time() - t0:.0f} s)", flush=True)
-    blob = export_blob(model)
-    np.save(args.out, blob, allow_pickle=False)
-    meta = {"steps": args.steps, "batch": args.batch, "patch": args.patch, "volumes": args.volumes,
-            "shape": shape, "sigma": args.sigma, "rho": args.rho, "seed": args.seed,
-            "in_scale": IN_SCALE, "in_offset": IN_OFFSET, "values": int(blob.size),
+    origins = patch_origins(torch, pool, args.patches, args.patch, args.min_weight, args.seed + 1)
+    print(f"pool of {args.volumes} labelled {shape} volumes, {len(origins)} patches in {time.time() - t0:.1f} s",
+          flush=True)
+    rng = np.random.default_rng(args.seed + 2)
+    blob = np.load(args.init, allow_pickle=False).astype(np.float32) if args.init else init_blob(rng)
+    params = torch.from_numpy(blob).to(dev)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    stats = torch.empty(8, dtype=torch.float32, device=dev)
+    ws = torch.empty(st.st_surrogate_grad_workspace_bytes(args.batch, args.patch), dtype=torch.uint8, device=dev)
+    gather = Gatherer(torch, pool, args.patch, args.batch, dev)
+    per_epoch = len(origins) // args.batch
+    steps = max(1, int(round(args.epochs * per_epoch)))
+    log_every = max(1, steps // 40)
+    acc = torch.zeros(8, dtype=torch.float64, device=dev)
+    order = rng.permutation(len(origins))
+    pos = 0
+    t1 = time.time()
+    for step in range(1, steps + 1):
+        if pos + args.batch > len(order):
+            order, pos = rng.permutation(len(origins)), 0
+        vol, e3, fa, w = gather(origins[order[pos:pos + args.batch]])
+        pos += args.batch
+        st.st_surrogate_grad(vol, e3, fa, w, params, grad=grad, stats=stats, workspace=ws)
+        acc += stats.double()
+        warm = min(1.0, step / args.warmup)
+        lr = args.lr * warm * 0.5 * (1.0 + math.cos(math.pi * step / steps))
+        st.st_surrogate_adam(params, grad, m, v, step, lr)
+        if step % log_every == 0 or step == steps:
+            a = (acc / log_every).cpu().numpy()
+            acc.zero_()
+            print(f"step {step}/{steps}: loss {a[3]:.4f} dir {a[0]:.4f} fa {a[1]:.5f} conf {a[2]:.4f} "
+                  f"within 2 deg {a[5] / max(a[4], 1):.3f} mean angle {math.degrees(a[6]):.2f} deg "
+                  f"lr {lr:.2e} ({time.time() - t1:.0f} s)", flush=True)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    out = params.cpu().numpy().astype(np.float32)
+    np.save(args.out, out, allow_pickle=False)
+    ev = evaluate(torch, st, helix, params, args.eval_volumes, shape, args.sigma, args.rho, args.seed + 1000, dev)
+    meta = {"trainer": "st_surrogate_grad + st_surrogate_adam", "patches": int(len(origins)),
+            "epochs": args.epochs, "steps": steps, "batch": args.batch, "patch": args.patch,
+            "volumes": args.volumes, "shape": list(shape), "sigma": args.sigma, "rho": args.rho,
+            "lr": args.lr, "warmup": args.warmup, "min_weight": args.min_weight, "seed": args.seed,
+            "in_scale": IN_SCALE, "in_offset": IN_OFFSET, "values": int(out.size),
+            "train_seconds": round(train_s, 1), "ms_per_step": round(1e3 * train_s / steps, 3),
+            "held_out": {"volumes": args.eval_volumes, "seed": args.seed + 1000, **ev},
             "seconds": round(time.time() - t0, 1)}
     with open(args.out + ".json", "w") as fh:
         json.dump(meta, fh, indent=1)

@@ -1,0 +1,466 @@
+// Stand-ins for the library's kernel launch functions (see hostcheck.h).  Each
+// checks the launch the way the kernel indexes memory: the grid it derives
+// from its parameters covers the volume, every buffer holds the furthest
+// element the kernel reads or writes, the compiled variant exists for the
+// radius and tile shape, and the grid fits HIP's limit.  Then the launch is
+// recorded on its stream.
+#include <cstdlib>
+#include <string>
+#include <cstring>
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+
+#include "hostcheck.h"
+#include "st_internal.h"
+#include "st_surrogate.h"
+
+namespace {
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void grid_ok(int64_t blocks, const char* what) {
+  if (blocks < 1 || blocks > INT32_MAX) hc::violation("%s: grid of %lld blocks", what, (long long)blocks);
+}
+
+bool compiled_sigma(int R) {
+  switch (R) {
+#define ST_C(r) case r:
+    ST_RADII_SIGMA(ST_C)
+    return true;
+    default:
+      return false;
+  }
+}
+
+bool compiled_rho(int R) {
+  switch (R) {
+    ST_RADII_RHO(ST_C)
+#undef ST_C
+    return true;
+    default:
+      return false;
+  }
+}
+
+}  // namespace
+
+namespace st {
+
+namespace {
+
+void check_grad(int R, int in_dtype, const GradGeo& p) {
+  const char* k = "k_grad_fused";
+  if (R < 1 || R > kGradMaxRadius || !compiled_sigma(R)) hc::violation("%s: radius %d not compiled", k, R);
+  if (!grad_rows_supported(R, p.rows)) hc::violation("%s: %d tile rows not compiled at radius %d", k, p.rows, R);
+  if (p.nz < 1 || p.ny < 1 || p.nx < 1 || p.ny * p.nx > INT32_MAX) hc::violation("%s: sizes", k);
+  if (p.x_tiles != cdiv(p.nx, kGradTX) || p.y_tiles != cdiv(p.ny, p.rows)) hc::violation("%s: tiles", k);
+  if (p.chunk < 1 || p.nchunks < 1 || p.chunk * p.nchunks < p.nz || p.chunk * (p.nchunks - 1) >= p.nz)
+    hc::violation("%s: z chunks %lld x %d for %lld planes", k, (long long)p.chunk, p.nchunks, (long long)p.nz);
+  if (p.opitch < p.nx) hc::violation("%s: pitch %lld < nx %lld", k, (long long)p.opitch, (long long)p.nx);
+  const size_t esz = in_dtype == ST_DTYPE_U16 ? 2 : 4;
+  hc::need(p.vol, static_cast<size_t>(p.nz * p.ny * p.nx) * esz, "k_grad_fused volume");
+  const size_t out = static_cast<size_t>((p.nz - 1) * p.ny * p.opitch + (p.ny - 1) * p.opitch + p.nx) * 4;
+  for (int c = 0; c < 6; ++c) hc::need(p.prod[c], out, "k_grad_fused product plane");
+}
+
+void check_strided(int R, int in_dtype, bool with_d, const StridedGeo& p) {
+  const char* k = "k_strided";
+  if (with_d ? !compiled_sigma(R) : !compiled_rho(R)) hc::violation("%s: radius %d not compiled", k, R);
+  if (in_dtype == ST_DTYPE_U16 && !with_d) hc::violation("%s: u16 input only in the gradient variant", k);
+  if (p.njobs < 1 || p.njobs > 6) hc::violation("%s: %d jobs", k, p.njobs);
+  if (p.x_tiles != cdiv(p.nx, 64) || p.o_tiles != cdiv(p.n_other, 4)) hc::violation("%s: tiles", k);
+  if (p.chunk < 1 || p.nchunks < 1 || p.chunk * p.nchunks < p.n_axis || p.chunk * (p.nchunks - 1) >= p.n_axis)
+    hc::violation("%s: chunks", k);
+  const bool same = p.so_axis == p.s_axis && p.so_other == p.s_other;
+  if (!same && !with_d) hc::violation("%s: own output strides need the two-output variant", k);
+  const size_t esz = in_dtype == ST_DTYPE_U16 ? 2 : 4;
+  const size_t in_n = static_cast<size_t>((p.n_other - 1) * p.s_other + (p.n_axis - 1) * p.s_axis + p.nx);
+  const size_t out_n = static_cast<size_t>((p.n_other - 1) * p.so_other + (p.n_axis - 1) * p.so_axis + p.nx);
+  for (int j = 0; j < p.njobs; ++j) {
+    hc::need(p.job[j].in, in_n * esz, "k_strided input");
+    hc::need(p.job[j].out_g, out_n * 4, "k_strided output G");
+    if (with_d) hc::need(p.job[j].out_d, out_n * 4, "k_strided output D");
+  }
+}
+
+void check_xfinal(int R, const XFinalGeo& p) {
+  const char* k = "k_xfinal";
+  if (!compiled_rho(R)) hc::violation("%s: radius %d not compiled", k, R);
+  if (!xfinal_lanes_supported(R, p.tile_lanes)) hc::violation("%s: %d lanes at radius %d", k, p.tile_lanes, R);
+  if (p.nrows != p.nz * p.ny || p.n != p.nrows * p.nx || p.pitch < p.nx) hc::violation("%s: sizes", k);
+  if (p.x_tiles != cdiv(p.nx, p.tile_lanes * kXVec)) hc::violation("%s: tiles", k);
+  const size_t sn = static_cast<size_t>((p.nrows - 1) * p.pitch + p.nx) * 4;
+  for (int c = 0; c < 6; ++c) hc::need(p.s[c], sn, "k_xfinal tensor plane");
+  const size_t n = static_cast<size_t>(p.n);
+  if (p.mask) hc::need(p.mask, n, "k_xfinal mask");
+  if (p.e3) hc::need(p.e3, 3 * n * 4, "k_xfinal e3");
+  if (p.evals) hc::need(p.evals, 3 * n * 4, "k_xfinal evals");
+  if (p.fa) hc::need(p.fa, n * 4, "k_xfinal fa");
+  if (p.ha) hc::need(p.ha, n * 4, "k_xfinal ha");
+  if (p.ia) hc::need(p.ia, n * 4, "k_xfinal ia");
+  if (p.flags) hc::need(p.flags, n, "k_xfinal flags");
+  if ((p.ha || p.ia) && !p.has_axis) hc::violation("%s: angles without an axis", k);
+  if (p.vec_ok)
+    for (const void* q : {(const void*)p.e3, (const void*)p.evals, (const void*)p.fa, (const void*)p.ha,
+                          (const void*)p.ia})
+      if (q && reinterpret_cast<uintptr_t>(q) % 16) hc::violation("%s: vec_ok with an unaligned output", k);
+}
+
+// The tables of a grouped launch: live buffers, block ranges that start at 0,
+// never shrink, end at the launch's grid and hold each entry's own grid
+// (starting on a multiple of `align`); returns the host-visible entries.
+template <class Geo>
+const Geo* check_group(const Grouped<Geo>& g, int64_t blocks, int64_t (*own)(const Geo&), int64_t align,
+                       const char* k) {
+  if (g.count < 1) hc::violation("%s: grouped launch of %d entries", k, g.count);
+  hc::need(g.geo, sizeof(Geo) * g.count, "grouped entry table");
+  hc::need(g.first, sizeof(int64_t) * (g.count + 1), "grouped block table");
+  if (g.first[0] != 0 || g.first[g.count] != blocks) hc::violation("%s: block table does not span the grid", k);
+  for (int e = 0; e < g.count; ++e) {
+    if (g.first[e] % align) hc::violation("%s: entry %d starts off a multiple of %lld", k, e, (long long)align);
+    if (g.first[e + 1] - g.first[e] < own(g.geo[e]))
+      hc::violation("%s: entry %d holds %lld blocks, its volume needs %lld", k, e,
+                    (long long)(g.first[e + 1] - g.first[e]), (long long)own(g.geo[e]));
+  }
+  grid_ok(blocks, k);
+  return g.geo;
+}
+
+int64_t own_grad(const GradGeo& g) { return grad_blocks(g); }
+int64_t own_strided(const StridedGeo& g) { return strided_blocks(g); }
+int64_t own_xfinal(const XFinalGeo& g) { return xfinal_blocks(g); }
+
+}  // namespace
+
+hipError_t launch_grad_fused(int R, int in_dtype, const GradFusedParams& p, hipStream_t stream) {
+  check_grad(R, in_dtype, p);
+  grid_ok(grad_blocks(p), "k_grad_fused");
+  hc::kernel_launch(stream, "k_grad_fused");
+  return hipSuccess;
+}
+
+hipError_t launch_grad_fused_grouped(int R, int in_dtype, int rows, const GradFusedGroup& p, int64_t blocks,
+                                     hipStream_t stream) {
+  const GradGeo* geo = check_group(p.g, blocks, own_grad, 8, "k_grad_fused_grouped");
+  for (int e = 0; e < p.g.count; ++e) {
+    if (geo[e].rows != rows) hc::violation("k_grad_fused_grouped: entry %d has %d tile rows", e, geo[e].rows);
+    check_grad(R, in_dtype, geo[e]);
+  }
+  hc::kernel_launch(stream, "k_grad_fused_grouped");
+  return hipSuccess;
+}
+
+hipError_t launch_strided(int R, int in_dtype, bool with_d, const StridedParams& p, hipStream_t stream) {
+  check_strided(R, in_dtype, with_d, p);
+  grid_ok(strided_blocks(p), "k_strided");
+  hc::kernel_launch(stream, "k_strided");
+  return hipSuccess;
+}
+
+hipError_t launch_strided_grouped(int R, const StridedGroup& p, int64_t blocks, hipStream_t stream) {
+  const StridedGeo* geo = check_group(p.g, blocks, own_strided, 1, "k_strided_grouped");
+  for (int e = 0; e < p.g.count; ++e) {
+    const StridedGeo& q = geo[e];
+    if (q.njobs != 6 || q.so_axis != q.s_axis || q.so_other != q.s_other)
+      hc::violation("k_strided_grouped: entry %d is not a six-component pass with shared strides", e);
+    check_strided(R, ST_DTYPE_F32, false, q);
+  }
+  hc::kernel_launch(stream, "k_strided_grouped");
+  return hipSuccess;
+}
+
+hipError_t launch_xgrad(int R, const XGradParams& p, hipStream_t stream) {
+  const char* k = "k_xgrad";
+  if (!compiled_sigma(R)) hc::violation("%s: radius %d not compiled", k, R);
+  if (p.x_tiles != cdiv(p.nx, kXTile) || p.pitch < p.nx) hc::violation("%s: tiles / pitch", k);
+  const size_t n = static_cast<size_t>((p.nrows - 1) * p.pitch + p.nx) * 4;
+  hc::need(p.gg, n, "k_xgrad input");
+  hc::need(p.dg, n, "k_xgrad input");
+  hc::need(p.gd, n, "k_xgrad input");
+  for (int c = 0; c < 6; ++c) hc::need(p.prod[c], n, "k_xgrad product plane");
+  grid_ok(p.x_tiles * p.nrows, k);
+  hc::kernel_launch(stream, k);
+  return hipSuccess;
+}
+
+hipError_t launch_xfinal(int R, const XFinalParams& p, hipStream_t stream) {
+  check_xfinal(R, p);
+  grid_ok(xfinal_blocks(p), "k_xfinal");
+  hc::kernel_launch(stream, "k_xfinal");
+  return hipSuccess;
+}
+
+hipError_t launch_xfinal_grouped(int R, int lanes, const XFinalGroup& p, int64_t blocks, hipStream_t stream) {
+  const XFinalGeo* geo = check_group(p.g, blocks, own_xfinal, 1, "k_xfinal_grouped");
+  for (int e = 0; e < p.g.count; ++e) {
+    if (geo[e].tile_lanes != lanes) hc::violation("k_xfinal_grouped: entry %d has %d lanes", e, geo[e].tile_lanes);
+    check_xfinal(R, geo[e]);
+  }
+  hc::kernel_launch(stream, "k_xfinal_grouped");
+  return hipSuccess;
+}
+
+hipError_t launch_angles(const AnglesParams& p, hipStream_t stream) {
+  const char* k = "k_angles";
+  if (p.n != p.nrows * p.nx || p.x_tiles != cdiv(p.nx, kXTile)) hc::violation("%s: sizes", k);
+  const size_t n = static_cast<size_t>(p.n);
+  hc::need(p.e3, 3 * n * 4, "k_angles e3");
+  if (p.mask) hc::need(p.mask, n, "k_angles mask");
+  if (p.ha) hc::need(p.ha, n * 4, "k_angles ha");
+  if (p.ia) hc::need(p.ia, n * 4, "k_angles ia");
+  if (p.flags) hc::need(p.flags, n, "k_angles flags");
+  grid_ok(p.x_tiles * cdiv(p.nrows, kRowsPerBlock), k);
+  hc::kernel_launch(stream, k);
+  return hipSuccess;
+}
+
+hipError_t launch_sg_pack(const float* blob, __bf16* w1, __bf16* w25, hipStream_t stream) {
+  hc::need(blob, ST_SURROGATE_WEIGHTS * 4, "k_sg_pack blob");
+  hc::need(w1, kSgChannels * 32 * 2, "k_sg_pack first-layer weights");
+  hc::need(w25, 4 * 27 * kSgChannels * kSgChannels * 2, "k_sg_pack layer weights");
+  hc::kernel_launch(stream, "k_sg_pack");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_conv(int layer, int dtype, const SgConvParams& p, hipStream_t stream) {
+  const char* k = "k_sg_conv";
+  if (layer < 1 || layer > kSgLayers) hc::violation("%s: layer %d", k, layer);
+  if (p.n != p.nz * p.ny * p.nx || p.x_tiles != cdiv(p.nx, 32) || p.y_tiles != cdiv(p.ny, 8) || p.zchunk < 1)
+    hc::violation("%s: sizes / tiles", k);
+  const size_t n = static_cast<size_t>(p.n);
+  const size_t act = n * kSgChannels * 2;
+  if (layer == 1) {
+    hc::need(p.vol, n * (dtype == ST_DTYPE_U16 ? 2 : 4), "k_sg_conv volume");
+    hc::need(p.w1, kSgChannels * 32 * 2, "k_sg_conv first-layer weights");
+    hc::need(p.scale_offset, 8, "k_sg_conv input map");
+  } else {
+    hc::need(p.in, act, "k_sg_conv input activations");
+    hc::need(p.w, 27 * kSgChannels * kSgChannels * 2, "k_sg_conv weights");
+  }
+  hc::need(p.bias, kSgChannels * 4, "k_sg_conv bias");
+  if (layer < kSgLayers) {
+    hc::need(p.out, act, "k_sg_conv output activations");
+    if (p.in && p.in == p.out) hc::violation("%s: layer %d reads and writes one buffer", k, layer);
+  } else {
+    hc::need(p.head_w, 5 * kSgChannels * 4, "k_sg_conv head weights");
+    hc::need(p.head_b, 5 * 4, "k_sg_conv head bias");
+    if (p.mask) hc::need(p.mask, n, "k_sg_conv mask");
+    if (p.e3) hc::need(p.e3, 3 * n * 4, "k_sg_conv e3");
+    if (p.fa) hc::need(p.fa, n * 4, "k_sg_conv fa");
+    if (p.ha) hc::need(p.ha, n * 4, "k_sg_conv ha");
+    if (p.ia) hc::need(p.ia, n * 4, "k_sg_conv ia");
+    if (p.conf) hc::need(p.conf, n * 4, "k_sg_conv confidence");
+    if ((p.ha || p.ia) && !p.has_axis) hc::violation("%s: angles without an axis", k);
+  }
+  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.nz, p.zchunk), k);
+  hc::kernel_launch(stream, k);
+  return hipSuccess;
+}
+
+hipError_t launch_sg_conv_hidden(bool first, int dtype, const SgConvParams& p, hipStream_t stream) {
+  const char* k = "k_sg_conv (training)";
+  if (p.n != p.nz * p.ny * p.nx || p.x_tiles != cdiv(p.nx, 32) || p.y_tiles != cdiv(p.ny, 8) || p.zchunk < 1)
+    hc::violation("%s: sizes / tiles", k);
+  const size_t n = static_cast<size_t>(p.n), act = n * kSgChannels * 2;
+  if (first) {
+    hc::need(p.vol, n * (dtype == ST_DTYPE_U16 ? 2 : 4), "k_sg_conv volume");
+    hc::need(p.w1, kSgChannels * 32 * 2, "k_sg_conv first-layer weights");
+    hc::need(p.scale_offset, 8, "k_sg_conv input map");
+  } else {
+    hc::need(p.in, act, "k_sg_conv input activations");
+    hc::need(p.w, 27 * kSgChannels * kSgChannels * 2, "k_sg_conv weights");
+  }
+  hc::need(p.bias, kSgChannels * 4, "k_sg_conv bias");
+  hc::need(p.out, act, "k_sg_conv output activations");
+  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.nz, p.zchunk), k);
+  hc::kernel_launch(stream, k);
+  return hipSuccess;
+}
+
+hipError_t launch_sg_conv_bwd(const SgConvParams& p, hipStream_t stream) {
+  const char* k = "k_sg_conv (backward)";
+  const size_t act = static_cast<size_t>(p.n) * kSgChannels * 2;
+  hc::need(p.in, act, "k_sg_conv backward input gradient");
+  hc::need(p.prev, act, "k_sg_conv backward activation mask");
+  hc::need(p.out, act, "k_sg_conv backward output gradient");
+  hc::need(p.w, 27 * kSgChannels * kSgChannels * 2, "k_sg_conv backward weights");
+  if (p.in == p.out || p.prev == p.out) hc::violation("%s: reads and writes one buffer", k);
+  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.nz, p.zchunk), k);
+  hc::kernel_launch(stream, k);
+  return hipSuccess;
+}
+
+hipError_t launch_sg_pack_bwd(const float* blob, __bf16* w25t, hipStream_t stream) {
+  hc::need(blob, ST_SURROGATE_WEIGHTS * 4, "k_sg_pack_bwd blob");
+  hc::need(w25t, 4 * 27 * kSgChannels * kSgChannels * 2, "k_sg_pack_bwd weights");
+  hc::kernel_launch(stream, "k_sg_pack_bwd");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_head_train(const SgHeadParams& p, int blocks, hipStream_t stream) {
+  const size_t n = static_cast<size_t>(p.n);
+  hc::need(p.x5, n * kSgChannels * 2, "k_sg_head_train x5");
+  hc::need(p.g5, n * kSgChannels * 2, "k_sg_head_train g5");
+  hc::need(p.head_w, 5 * kSgChannels * 4, "k_sg_head_train head weights");
+  hc::need(p.head_b, 5 * 4, "k_sg_head_train head bias");
+  hc::need(p.target, 3 * n * 4, "k_sg_head_train target");
+  hc::need(p.target_fa, n * 4, "k_sg_head_train target FA");
+  hc::need(p.weight, n, "k_sg_head_train weight");
+  hc::need(p.partial, static_cast<size_t>(blocks) * kSgHeadSums * 4, "k_sg_head_train partial");
+  grid_ok(blocks, "k_sg_head_train");
+  hc::kernel_launch(stream, "k_sg_head_train");
+  return hipSuccess;
+}
+
+namespace {
+void check_wgrad(const SgWgradParams& p, int blocks, size_t per_block, const char* k) {
+  if (p.nx < 1 || p.nx > kSgTrainMaxX) hc::violation("%s: rows of %lld voxels", k, (long long)p.nx);
+  if (p.rows_per_block * blocks < p.nz * p.ny) hc::violation("%s: blocks do not cover the rows", k);
+  hc::need(p.g, static_cast<size_t>(p.nz * p.ny * p.nx) * kSgChannels * 2, "wgrad gradient");
+  hc::need(p.partial, static_cast<size_t>(blocks) * per_block * 4, "wgrad partial");
+  grid_ok(blocks, k);
+}
+}  // namespace
+
+hipError_t launch_sg_wgrad(const SgWgradParams& p, int blocks, hipStream_t stream) {
+  check_wgrad(p, blocks, 27 * kSgChannels * kSgChannels + kSgChannels, "k_sg_wgrad");
+  hc::need(p.x, static_cast<size_t>(p.nz * p.ny * p.nx) * kSgChannels * 2, "k_sg_wgrad activation");
+  hc::kernel_launch(stream, "k_sg_wgrad");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_wgrad1(int dtype, const SgWgradParams& p, int blocks, hipStream_t stream) {
+  check_wgrad(p, blocks, 27 * kSgChannels + kSgChannels, "k_sg_wgrad1");
+  hc::need(p.vol, static_cast<size_t>(p.nz * p.ny * p.nx) * (dtype == ST_DTYPE_U16 ? 2 : 4), "k_sg_wgrad1 volume");
+  hc::need(p.scale_offset, 8, "k_sg_wgrad1 input map");
+  hc::kernel_launch(stream, "k_sg_wgrad1");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_reduce(const float* partial, int blocks, int len, int mode, float* out, hipStream_t stream) {
+  hc::need(partial, static_cast<size_t>(blocks) * len * 4, "k_sg_reduce partial");
+  hc::need(out, static_cast<size_t>(len) * 4, "k_sg_reduce output");
+  if (mode != 0 && mode != 1) hc::violation("k_sg_reduce: mode %d", mode);
+  hc::kernel_launch(stream, "k_sg_reduce");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float* stats, hipStream_t stream) {
+  hc::need(grad, static_cast<size_t>(n) * 4, "k_sg_finish gradient");
+  hc::need(raw, 6 * 4, "k_sg_finish sums");
+  hc::need(stats, kSgTrainStats * 4, "k_sg_finish stats");
+  hc::kernel_launch(stream, "k_sg_finish");
+  hc::kernel_launch(stream, "k_sg_stats");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_adam(float* params, const float* grad, float* m, float* v, int64_t n, int64_t frozen,
+                          int64_t step, float, float, float, float, hipStream_t stream) {
+  for (const float* q : {(const float*)params, grad, (const float*)m, (const float*)v})
+    hc::need(q, static_cast<size_t>(n) * 4, "k_sg_adam buffer");
+  if (step < 1 || frozen < 0 || frozen > n) hc::violation("k_sg_adam: step %lld, frozen %lld", (long long)step,
+                                                          (long long)frozen);
+  hc::kernel_launch(stream, "k_sg_adam");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_merge(const SgMergeParams& p, hipStream_t stream) {
+  const size_t n = static_cast<size_t>(p.n);
+  hc::need(p.conf, n * 4, "k_sg_merge confidence");
+  if (p.mask) hc::need(p.mask, n, "k_sg_merge mask");
+  if (p.e3) { hc::need(p.e3, 3 * n * 4, "k_sg_merge e3"); hc::need(p.pe3, 3 * n * 4, "k_sg_merge plain e3"); }
+  if (p.fa) { hc::need(p.fa, n * 4, "k_sg_merge fa"); hc::need(p.pfa, n * 4, "k_sg_merge plain fa"); }
+  if (p.ha) { hc::need(p.ha, n * 4, "k_sg_merge ha"); hc::need(p.pha, n * 4, "k_sg_merge plain ha"); }
+  if (p.ia) { hc::need(p.ia, n * 4, "k_sg_merge ia"); hc::need(p.pia, n * 4, "k_sg_merge plain ia"); }
+  grid_ok(cdiv(p.n, 256), "k_sg_merge");
+  hc::kernel_launch(stream, "k_sg_merge");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_tile_flags(const SgTileFlagParams& p, hipStream_t stream) {
+  const size_t n = static_cast<size_t>(p.nz * p.ny * p.nx);
+  hc::need(p.conf, n * 4, "k_sg_tile_flags confidence");
+  if (p.mask) hc::need(p.mask, n, "k_sg_tile_flags mask");
+  for (int k = 0; k < kSgTileEdges; ++k) {
+    const int64_t t = int64_t(32) << k;
+    const int64_t want = cdiv(p.nz, t) * cdiv(p.ny, t) * cdiv(p.nx, t);
+    if (p.tiles[k] != want) hc::violation("k_sg_tile_flags: grid %d has %lld tiles, not %lld", k,
+                                          (long long)p.tiles[k], (long long)want);
+    hc::need(p.flags[k], static_cast<size_t>(p.tiles[k]) * 4, "k_sg_tile_flags flags");
+    // a deterministic pattern stands in for the confidence test (HOSTCHECK_FLAGS:
+    // "none", "all", "one" (the last tile), else every third tile)
+    const char* m = std::getenv("HOSTCHECK_FLAGS");
+    const std::string mode = m ? m : "";
+    for (int64_t i = 0; i < p.tiles[k]; ++i)
+      p.flags[k][i] = mode == "none" ? 0 : mode == "all" ? 1 : mode == "one" ? (i == p.tiles[k] - 1) : (i % 3 == 0);
+    hc::kernel_launch(stream, "k_sg_fill_zero");
+  }
+  grid_ok(cdiv(p.nz * p.ny * cdiv(p.nx, 64), 4), "k_sg_tile_flags");
+  hc::kernel_launch(stream, "k_sg_tile_flags");
+  return hipSuccess;
+}
+
+namespace {
+// Boxes and row tables as the kernels read them (the stub sees device memory).
+void check_boxes(const SgBox* boxes, const int64_t* first, int count, int64_t rows, bool interior, const char* k) {
+  hc::need(boxes, static_cast<size_t>(count) * sizeof(SgBox), "crop boxes");
+  hc::need(first, static_cast<size_t>(count) * 8, "crop row table");
+  int64_t r = 0, off = 0;
+  for (int c = 0; c < count; ++c) {
+    const SgBox& b = boxes[c];
+    if (first[c] != r) hc::violation("%s: crop %d starts at row %lld, not %lld", k, c, (long long)first[c], (long long)r);
+    if (b.off != off) hc::violation("%s: crop %d at voxel %lld, not %lld", k, c, (long long)b.off, (long long)off);
+    if (b.cz < 1 || b.cy < 1 || b.cx < 1 || b.z0 < 0 || b.y0 < 0 || b.x0 < 0)
+      hc::violation("%s: crop %d is empty or starts outside the volume", k, c);
+    if (b.tz0 < b.z0 || b.ty0 < b.y0 || b.tx0 < b.x0 || b.tz1 > b.z0 + b.cz || b.ty1 > b.y0 + b.cy ||
+        b.tx1 > b.x0 + b.cx || b.tz1 <= b.tz0 || b.ty1 <= b.ty0 || b.tx1 <= b.tx0)
+      hc::violation("%s: tile %d does not lie inside its crop", k, c);
+    r += interior ? (b.tz1 - b.tz0) * (b.ty1 - b.ty0) : b.cz * b.cy;
+    off += b.cz * b.cy * b.cx;
+  }
+  if (r != rows) hc::violation("%s: %lld rows, tables give %lld", k, (long long)rows, (long long)r);
+}
+}  // namespace
+
+hipError_t launch_sg_gather(int dtype, const SgGatherParams& p, hipStream_t stream) {
+  check_boxes(p.boxes, p.first, p.count, p.rows, false, "k_sg_gather");
+  const size_t esz = dtype == ST_DTYPE_U16 ? 2 : 4;
+  const SgBox& last = p.boxes[p.count - 1];
+  const size_t stack = static_cast<size_t>(last.off + last.cz * last.cy * last.cx);
+  int64_t zmax = 0;
+  for (int c = 0; c < p.count; ++c) {
+    const SgBox& b = p.boxes[c];
+    if (b.y0 + b.cy > p.ny || b.x0 + b.cx > p.nx) hc::violation("k_sg_gather: crop %d leaves the volume", c);
+    zmax = std::max(zmax, b.z0 + b.cz);
+  }
+  hc::need(p.vol, static_cast<size_t>(zmax * p.ny * p.nx) * esz, "k_sg_gather volume");
+  hc::need(p.cvol, stack * esz, "k_sg_gather crop stack");
+  if ((p.mask == nullptr) != (p.cmask == nullptr)) hc::violation("k_sg_gather: mask without crop mask");
+  if (p.mask) {
+    hc::need(p.mask, static_cast<size_t>(zmax * p.ny * p.nx), "k_sg_gather mask");
+    hc::need(p.cmask, stack, "k_sg_gather crop mask");
+  }
+  grid_ok(p.rows, "k_sg_gather");
+  hc::kernel_launch(stream, "k_sg_gather");
+  return hipSuccess;
+}
+
+hipError_t launch_sg_tile_merge(const SgTileMergeParams& p, hipStream_t stream) {
+  check_boxes(p.boxes, p.first, p.count, p.rows, true, "k_sg_tile_merge");
+  const SgBox& last = p.boxes[p.count - 1];
+  const size_t stack = static_cast<size_t>(last.off + last.cz * last.cy * last.cx), n = static_cast<size_t>(p.n);
+  for (int c = 0; c < p.count; ++c)
+    if ((p.boxes[c].z0 + p.boxes[c].cz) * p.ny * p.nx > p.n) hc::violation("k_sg_tile_merge: crop %d leaves the volume", c);
+  hc::need(p.conf, n * 4, "k_sg_tile_merge confidence");
+  if (p.mask) hc::need(p.mask, n, "k_sg_tile_merge mask");
+  if (p.e3) { hc::need(p.e3, 3 * n * 4, "k_sg_tile_merge e3"); hc::need(p.pe3, 3 * stack * 4, "k_sg_tile_merge crop e3"); }
+  if (p.fa) { hc::need(p.fa, n * 4, "k_sg_tile_merge fa"); hc::need(p.pfa, stack * 4, "k_sg_tile_merge crop fa"); }
+  if (p.ha) { hc::need(p.ha, n * 4, "k_sg_tile_merge ha"); hc::need(p.pha, stack * 4, "k_sg_tile_merge crop ha"); }
+  if (p.ia) { hc::need(p.ia, n * 4, "k_sg_tile_merge ia"); hc::need(p.pia, stack * 4, "k_sg_tile_merge crop ia"); }
+  grid_ok(p.rows, "k_sg_tile_merge");
+  hc::kernel_launch(stream, "k_sg_tile_merge");
+  return hipSuccess;
+}
+
+}  // namespace st

@@ -179,6 +179,8 @@ def test_batch_workspace_bytes(lib):
     assert slot == 21504
     assert lib.st_batch_workspace_bytes(arr, 2, 3) == 3 * slot
     assert lib.st_batch_workspace_bytes(arr, 2, 0) == B.ST_BATCH_MAX_LANES * slot
+    assert lib.st_batch_workspace_bytes(arr, 2, B.ST_BATCH_GROUPED) == B.ST_BATCH_MAX_LANES * slot
+    assert lib.st_batch_workspace_bytes(arr, 2, -2) == 0
     assert lib.st_batch_workspace_bytes(arr, 2, 9) == 0
     assert lib.st_batch_workspace_bytes(arr, 0, 1) == 0
     assert lib.st_batch_workspace_bytes(_chunks(dict(nz=0)), 1, 1) == 0
@@ -198,7 +200,7 @@ def _create(lib, arr, n, lanes=1, center=None, direction=None, ws=None, ws_bytes
     (dict(out=False), "out is NULL"),
     (dict(n=0), "at least one chunk"),
     (dict(lanes=9), "lanes"),
-    (dict(lanes=-1), "lanes"),
+    (dict(lanes=-2), "lanes"),
     (dict(center=(1, 2, 3)), "both"),
     (dict(specs=[{}, dict(rho=0.0)]), "chunk 1"),
     (dict(specs=[dict(nx=0)]), "sizes"),
@@ -221,6 +223,7 @@ def test_batch_calls_reject_null_handle(lib):
     assert lib.st_batch_tune(None, None, 1) == B.ST_ERR_INVALID_ARG
     assert lib.st_batch_config(None, None, None, None, None, None) == B.ST_ERR_INVALID_ARG
     assert lib.st_batch_tiles(None, 0, None, None) == B.ST_ERR_INVALID_ARG
+    assert lib.st_batch_plan(None, None, None, None) == B.ST_ERR_INVALID_ARG
     assert lib.st_batch_destroy(None) == B.ST_OK
 
 

@@ -127,6 +127,41 @@ def test_batch_replays_tuning_and_direct_enqueue_are_bitwise_stable(phantom):
     b.close()
 
 
+def test_grouped_batch_matches_chains_bitwise(phantom):
+    """Grouped launches (each pass one kernel over a round of chunks, geometry
+    from a device table) give the same bits as the chains, replayed and direct;
+    with a workspace of two slots the chunks fall into several rounds."""
+    chunks = _chunks(phantom)
+    ref = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                   outputs=OUTS, lanes=3)
+    ref.launch()
+    want = _snapshot(ref)
+    ref.close()
+    shapes = [tuple(c["volume"].shape) for c in chunks]
+    for ws_lanes in (0, 2):
+        ws = torch.empty(st.Batch.workspace_bytes(shapes, lanes=ws_lanes or st.ST_BATCH_MAX_LANES),
+                         dtype=torch.uint8, device=DEV)
+        b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                     outputs=OUTS, lanes=st.ST_BATCH_GROUPED, workspace=ws)
+        plan = b.plan()
+        _log("case: grouped batch, workspace of", ws_lanes or st.ST_BATCH_MAX_LANES, "slots, plan", plan)
+        assert plan["grouped"] and plan["rounds"] >= 1
+        if ws_lanes == 2:
+            assert plan["rounds"] >= 2
+        for rep in range(2):
+            for r in b.results:
+                for v in r.values():
+                    v.zero_()
+            torch.cuda.synchronize()
+            b.launch()
+            got = _snapshot(b)
+            for i, (x, y) in enumerate(zip(got, want)):
+                for k in OUTS:
+                    assert torch.equal(x[k], y[k]), (ws_lanes, rep, i, k)
+        b.close()
+        del ws
+
+
 def test_batch_graph_replays_are_bitwise_stable(phantom):
     chunks = _chunks(phantom)
     b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],

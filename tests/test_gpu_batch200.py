@@ -3,7 +3,9 @@
 3 rho, rho in {2, 3, 4}, sigma 1) of the 512^3 uint16 phantom with its mask,
 3.0 G voxels in all, run as one batch of 8 graph-replayed chains.
 
-* Every chunk's outputs equal, bitwise, those of st_compute on the same crop.
+* Every chunk's outputs equal, bitwise, those of st_compute on the same crop,
+  and the grouped launches (one kernel per pass over a round of chunks) give
+  the same bits.
 * Each padded chunk is its own volume, reflected at its faces (the halo of
   3 rho is below R_sigma + R_rho, so a chunk is compared with the oracle run on
   the same padded crop, not with the whole volume).  The FP64 oracle checks the
@@ -141,7 +143,21 @@ def test_batch_of_200_chunks_bitwise_and_against_the_oracle():
         for k in OUTS:
             assert torch.equal(res[k], single[k]), (i, crops[i], k)
         del single
+    del ws
     _log("all 200 chunks bitwise equal to st_compute")
+    # the same chunks as grouped launches: bitwise equal to the chains
+    g = st.Batch(chunks, SIGMA, axis_center=ph["center"], axis_direction=ph["direction"], outputs=OUTS,
+                 lanes=st.ST_BATCH_GROUPED)
+    _log("grouped plan", g.plan())
+    g.launch()
+    torch.cuda.synchronize()
+    for i, (x, y) in enumerate(zip(g.results, b.results)):
+        for k in OUTS:
+            assert torch.equal(x[k], y[k]), ("grouped", i, k)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    _log("grouped launches bitwise equal to the chains")
 
     try:
         for (i, bo, shp), f in zip(jobs, futs):

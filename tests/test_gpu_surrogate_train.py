@@ -1,0 +1,147 @@
+"""Training kernels of the surrogate on the GPU (MI355X only), through the C
+ABI: the gradient of the training objective against the FP64 oracle (which
+rounds activations, stored gradients and weights to bf16 where the kernels
+do), for uint16 and float32 patches of 12^3, 16^3 and 24^3 voxels and one
+of 32^3 (the training size); and Adam steps that lower the objective on a
+fixed batch."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2508_07476_amd as st
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+MARGIN = 5
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _groups():
+    """(name, slice) of every weight group in the blob."""
+    out, i = [], 2
+    for layer in range(1, 6):
+        n = 32 * (1 if layer == 1 else 32) * 27
+        out.append((f"W{layer}", slice(i, i + n)))
+        i += n
+        out.append((f"b{layer}", slice(i, i + 32)))
+        i += 32
+    out.append(("Wh", slice(i, i + 160)))
+    out.append(("bh", slice(i + 160, i + 165)))
+    return out
+
+
+def _case(seed, npatch, P, dtype):
+    rng = np.random.default_rng(seed)
+    blob = np.zeros(S.n_weights())
+    blob[0], blob[1] = (4.0 / 65535.0, -2.0) if dtype == "u16" else (1.0, 0.0)
+    i = 2
+    for layer in range(1, 6):
+        cin = 1 if layer == 1 else 32
+        n = 32 * cin * 27
+        blob[i:i + n] = rng.normal(scale=np.sqrt(2.0 / (27 * cin)), size=n)
+        i += n
+        blob[i:i + 32] = rng.normal(scale=0.05, size=32)
+        i += 32
+    blob[i:i + 165] = rng.normal(scale=0.3, size=165)
+    shape = (npatch * P, P, P)
+    if dtype == "u16":
+        vol = rng.integers(0, 65536, size=shape).astype(np.uint16)
+    else:
+        vol = rng.uniform(-1.0, 1.0, size=shape).astype(np.float32)
+    t = rng.normal(size=(3,) + shape)
+    t /= np.linalg.norm(t, axis=0, keepdims=True)
+    fa = rng.uniform(0.05, 0.95, size=shape)
+    w = np.zeros(shape, dtype=np.uint8)
+    for b in range(npatch):
+        w[b * P + MARGIN:(b + 1) * P - MARGIN, MARGIN:P - MARGIN, MARGIN:P - MARGIN] = 1
+    w &= (rng.random(shape) < 0.9).astype(np.uint8)
+    return blob.astype(np.float32), vol, t.astype(np.float32), fa.astype(np.float32), w
+
+
+def _oracle(blob, vol, t, fa, w, npatch, P):
+    pt = vol.astype(np.float64).reshape(npatch, P, P, P)
+    tt = t.astype(np.float64).reshape(3, npatch, P, P, P).transpose(1, 0, 2, 3, 4)
+    return S.train_loss_grad(blob.astype(np.float64), pt, tt, fa.astype(np.float64).reshape(npatch, P, P, P),
+                             w.astype(np.float64).reshape(npatch, P, P, P))
+
+
+def _gpu(blob, vol, t, fa, w):
+    g, s = st.st_surrogate_grad(torch.from_numpy(vol).to(DEV), torch.from_numpy(t).to(DEV),
+                                torch.from_numpy(fa).to(DEV), torch.from_numpy(w).to(DEV),
+                                torch.from_numpy(blob).to(DEV))
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), s.cpu().numpy().astype(np.float64)
+
+
+# Tolerance: the kernels accumulate in float32 and round each stored activation
+# and gradient to bf16 as the oracle does, so the two differ by float32
+# rounding (~1e-7 relative) plus the rare bf16 value rounded the other way at a
+# tie of the two accumulation orders (one bf16 ulp, 2^-8 relative) and the rare
+# loss voxel whose 2-degree confidence target flips.  A flipped activation moves
+# its voxel's loss terms by at most about one bf16 ulp; averaged over the
+# patch's voxels, with signs that do not line up, that stays far below a
+# quarter ulp of the mean (LOSS_TOL relative).  Per weight group the gradient
+# stays far below 1 % of the group's norm.
+GROUP_TOL = 1e-2
+LOSS_TOL = 1e-3
+
+
+def _compare(g, s, o):
+    """Every check's figure, logged before any assertion."""
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1e-30)
+    got = {"loss_dir": rel(s[0], o["loss_dir"]), "loss_fa": rel(s[1], o["loss_fa"]),
+           "loss_conf": rel(s[2], o["loss_conf"]), "within": abs(s[5] - o["within"]),
+           "wsum": abs(s[4] - o["wsum"]) + abs(s[7] - o["wsum"])}
+    for name, sl in _groups():
+        ref = o["grad"][sl]
+        got[name] = float(np.linalg.norm(g[sl] - ref) / max(np.linalg.norm(ref), 1e-30))
+    _log({k: f"{v:.2e}" for k, v in got.items()})
+    assert got["wsum"] == 0, got
+    assert g[0] == 0 and g[1] == 0  # in_scale and in_offset are not trained
+    assert max(got["loss_dir"], got["loss_fa"], got["loss_conf"]) <= LOSS_TOL, got
+    assert got["within"] <= max(2, 1e-3 * o["wsum"]), got
+    groups = {k: v for k, v in got.items() if k[0] in "Wb"}
+    assert max(groups.values()) <= GROUP_TOL, groups
+
+
+@pytest.mark.parametrize("seed,npatch,P,dtype", [(1, 2, 16, "u16"), (2, 1, 24, "f32"), (3, 3, 12, "u16")])
+def test_gradient_matches_oracle(seed, npatch, P, dtype):
+    _log("case: surrogate gradient", npatch, "patches of", P, dtype)
+    blob, vol, t, fa, w = _case(seed, npatch, P, dtype)
+    g, s = _gpu(blob, vol, t, fa, w)
+    _compare(g, s, _oracle(blob, vol, t, fa, w, npatch, P))
+
+
+def test_training_size_patch():
+    """One patch of 32^3 (the training size: full 32-voxel MFMA rows), every
+    weight group against the oracle."""
+    blob, vol, t, fa, w = _case(7, 1, 32, "u16")
+    _log("case: surrogate gradient, one patch of 32^3")
+    g, s = _gpu(blob, vol, t, fa, w)
+    _compare(g, s, _oracle(blob, vol, t, fa, w, 1, 32))
+
+
+def test_adam_steps_lower_the_objective():
+    blob, vol, t, fa, w = _case(5, 2, 16, "u16")
+    _log("case: ten Adam steps on one batch")
+    params = torch.from_numpy(blob).to(DEV)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    args = (torch.from_numpy(vol).to(DEV), torch.from_numpy(t).to(DEV), torch.from_numpy(fa).to(DEV),
+            torch.from_numpy(w).to(DEV))
+    losses = []
+    frozen = params[:2].clone()
+    for step in range(1, 11):
+        g, s = st.st_surrogate_grad(*args, params)
+        losses.append(float(s[3]))
+        st.st_surrogate_adam(params, g, m, v, step, 1e-3)
+    torch.cuda.synchronize()
+    assert losses[-1] < losses[0], losses
+    assert torch.equal(params[:2], frozen)  # in_scale and in_offset are not trained
