@@ -196,8 +196,15 @@ int st_angles(const float* e3, const uint8_t* mask,
  * ia also when every axis_center coordinate minus an integer is exact in
  * double (e.g. a multiple of 1/2 below 2^50).  st_surrogate_fallback_info
  * reports which was taken.
- * Device workspace: 128 bytes per voxel of activations, taken with
- * hipMallocAsync on `stream` and released the same way; with a fallback, the
+ * The network runs in z slabs: two bf16 activation buffers of a slab plus 4
+ * planes on each side (64 bytes per voxel each; slabs as thick as keep both
+ * within 16 GiB, or within the byte count in the environment variable
+ * ST_SURROGATE_SLAB_BYTES, the whole volume when it fits), every layer
+ * computing only the planes the next one needs.  Results do not depend on the
+ * slab thickness (bit for bit).
+ * Device workspace: the two activation buffers, taken with hipMallocAsync on
+ * `stream` and released the same way once the network has run (before any
+ * fallback); with a fallback, the
  * crops (hipMalloc, about 75 bytes per crop voxel and their batch) or the
  * whole-volume path (hipMallocAsync, st_compute's workspace plus 24 bytes per
  * voxel).
@@ -346,9 +353,23 @@ int st_batch_config(const st_batch* batch, int* lanes, int* use_graph, int64_t* 
                     int64_t* strided_min_waves, double* best_ms);
 
 /* How the batch launches: grouped (1) or chains (0); the rounds of the grouped
- * mode (0 for chains); the kernel launches one st_batch_launch makes.  Any
- * output pointer may be NULL. */
+ * mode (0 for chains); the compute kernel launches one st_batch_launch makes
+ * (besides the completion record's one-thread kernels).  Any output pointer
+ * may be NULL. */
 int st_batch_plan(const st_batch* batch, int* grouped, int* rounds, int* kernels);
+
+/* Completion record, for resuming an interrupted batch (the paper saves every
+ * chunk's outputs as it finishes, so a run can resume by chunk).  After the
+ * last pass of each chunk (grouped launches: of each round) the GPU writes the
+ * batch's launch count into a pinned host word of that chunk.  This call reads
+ * those words without waiting for the GPU: done[c] = 1 when chunk c's outputs
+ * of the batch's latest launch are complete, else 0 (all 0 before the first
+ * launch); *launches = launches so far (st_batch_launch calls and the timing
+ * runs of st_batch_tune, which leave every chunk complete).  It may be called while a
+ * launch runs, or after one failed: a new batch of the chunks with done[c] = 0
+ * finishes the work.  done: HOST array of nchunks (the batch's chunk count)
+ * or NULL; launches may be NULL. */
+int st_batch_progress(const st_batch* batch, uint8_t* done, int nchunks, int64_t* launches);
 
 /* Tile shapes of chunk `chunk` (0 <= chunk < nchunks): the rows of a gradient
  * tile and the lanes of a final-pass row segment; 0 means the library's

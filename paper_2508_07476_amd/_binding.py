@@ -71,6 +71,7 @@ SIGNATURES = {
     "st_batch_plan": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_int)]),
     "st_batch_tiles": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "st_batch_progress": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "st_batch_destroy": (ctypes.c_int, [_P]),
     "st_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "st_profile_reset": (ctypes.c_int, []),
@@ -530,6 +531,15 @@ class Batch:
         rows, lanes = ctypes.c_int(), ctypes.c_int()
         _check(load_library().st_batch_tiles(self._handle(), int(chunk), ctypes.byref(rows), ctypes.byref(lanes)))
         return rows.value, lanes.value
+
+    def progress(self) -> tuple:
+        """(done, launches): done[c] is True when chunk c's outputs of the latest
+        launch are complete (read without waiting for the GPU)."""
+        n = len(self.results)
+        done = (ctypes.c_uint8 * n)()
+        launches = ctypes.c_int64()
+        _check(load_library().st_batch_progress(self._handle(), done, n, ctypes.byref(launches)))
+        return [bool(d) for d in done], launches.value
 
     def config(self) -> dict:
         lanes, graph = ctypes.c_int(), ctypes.c_int()

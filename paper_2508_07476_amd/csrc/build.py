@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libst.so")
 # groups so that the largest radii compile in parallel
 STRIDED_GROUPS = 8
 UNITS = ([("st_api.hip", [], "st_api"), ("st_batch.hip", [], "st_batch"), ("st_noalloc.hip", [], "st_noalloc"), ("st_surrogate.hip", [], "st_surrogate"),
-          ("k_surrogate.hip", [], "k_surrogate"), ("k_surrogate_train.hip", [], "k_surrogate_train"), ("k_sg_fallback.hip", [], "k_sg_fallback"), ("k_strided.hip", [], "k_strided"),
+          ("k_surrogate.hip", [], "k_surrogate"), ("k_surrogate_train.hip", [], "k_surrogate_train"), ("k_sg_fallback.hip", [], "k_sg_fallback"), ("k_batch.hip", [], "k_batch"), ("k_strided.hip", [], "k_strided"),
           ("k_xpass.hip", [], "k_xpass"), ("k_xgrad.hip", [], "k_xgrad"),
           ("k_xfinala.hip", [], "k_xfinala"), ("k_xfinalb.hip", [], "k_xfinalb"),
           ("k_angles.hip", [], "k_angles"), ("k_gradf.hip", [], "k_gradf")] +

@@ -54,12 +54,12 @@ struct ForkJoin {
 // shares its radius, taps and tile shape; its tables live in the batch's table
 // buffer.
 struct GroupLaunch {
-  int kind = 0;    // 0 gradient, 1 z integration, 2 y integration, 3 final pass
+  int kind = 0;    // 0 gradient, 1 z integration, 2 y integration, 3 final pass, 4 completion mark
   int R = 0;       // compiled radius
   int shape = 0;   // gradient tile rows, or final-pass segment lanes
   int dtype = 0;   // input type (gradient)
   st::Taps w0{}, w1{};  // gradient: smoothing, derivative taps; integration: smoothing taps
-  size_t geo = 0, first = 0;  // byte offsets of the entry table and the block table
+  size_t geo = 0, first = 0;  // byte offsets of the entry table (mark: chunk ids) and the block table
   int count = 0;
   int64_t blocks = 0;
 };
@@ -95,6 +95,11 @@ struct st_batch {
   int rounds = 0;
   std::vector<GroupLaunch> glaunch;
   char* tables = nullptr;  // device buffer of the entry and block tables (owned)
+  // completion record: a device launch counter and one pinned host word per
+  // chunk that takes the counter's value when the chunk's last pass is done
+  uint64_t* seq = nullptr;
+  uint64_t* progress = nullptr;
+  int64_t launches = 0;
 };
 
 namespace {
@@ -244,6 +249,18 @@ int plan_grouped(st_batch* b) {
         firsts.push_back(std::move(first));
       }
     }
+    // the round's chunks are complete once its launches have run
+    GroupLaunch M;
+    M.kind = 4;
+    M.count = static_cast<int>(rd.chunk_off.size());
+    std::vector<char> ids(rd.chunk_off.size() * sizeof(int64_t));
+    for (size_t k = 0; k < rd.chunk_off.size(); ++k) {
+      const int64_t c = rd.chunk_off[k].first;
+      std::memcpy(ids.data() + k * sizeof(int64_t), &c, sizeof(c));
+    }
+    launches.push_back(M);
+    geos.push_back(std::move(ids));
+    firsts.push_back(std::vector<int64_t>{0});
   }
   // one device buffer for every table, each 256-byte aligned
   size_t total = 0;
@@ -297,6 +314,10 @@ hipError_t enqueue_grouped(st_batch* b, hipStream_t stream, const char** stage) 
       g.wg = L.w0;
       *stage = L.kind == 1 ? "integrate_z (grouped)" : "integrate_y (grouped)";
       e = st::launch_strided_grouped(L.R, g, L.blocks, stream);
+    } else if (L.kind == 4) {
+      *stage = "completion mark";
+      e = st::launch_batch_mark(b->seq, b->progress, reinterpret_cast<const int64_t*>(b->tables + L.geo), L.count, 0,
+                                stream);
     } else {
       st::XFinalGroup g;
       g.g.geo = reinterpret_cast<const st::XFinalGeo*>(b->tables + L.geo);
@@ -321,9 +342,12 @@ hipError_t enqueue_all(st_batch* b, hipStream_t root, const ForkJoin& fj, const 
     hipStream_t s = b->lane_stream[k];
     if ((e = hipStreamWaitEvent(s, fj.fork, 0)) != hipSuccess) return e;
     char* ws = b->ws + static_cast<size_t>(k) * b->slot_bytes;
-    for (int i : b->plan[k])
+    for (int i : b->plan[k]) {
       if ((e = st::host::enqueue_path(b->chunks[i], ws, s, chunk_shape(b, i), false, stage)) != hipSuccess)
         return e;
+      *stage = "completion mark";
+      if ((e = st::launch_batch_mark(b->seq, b->progress, nullptr, 1, i, s)) != hipSuccess) return e;
+    }
     *stage = "join";
     if ((e = hipEventRecord(fj.join[k], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(root, fj.join[k], 0)) != hipSuccess) return e;
@@ -398,6 +422,8 @@ int launch(st_batch* b, hipStream_t stream) {
   hipError_t e = hipSuccess;
   const char* stage = "hipStreamWaitEvent";
   if (b->launched && (e = hipStreamWaitEvent(stream, b->done, 0)) != hipSuccess) return device_fail(e, stage);
+  stage = "launch counter";
+  if ((e = st::launch_batch_begin(b->seq, stream)) != hipSuccess) return device_fail(e, stage);
   stage = "hipGraphLaunch";
   if (b->use_graph) {
     e = hipGraphLaunch(b->captured->exec, stream);
@@ -410,6 +436,8 @@ int launch(st_batch* b, hipStream_t stream) {
     stage = "hipEventRecord";
     e = hipEventRecord(b->done, stream);
   }
+  // the counter was bumped: from here on the record refers to this launch
+  b->launches += 1;
   if (e != hipSuccess) return device_fail(e, stage);
   b->launched = true;
   return ST_OK;
@@ -427,6 +455,8 @@ void release(st_batch* b) {
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->owned && b->ws) (void)hipFree(b->ws);
   if (b->tables) (void)hipFree(b->tables);
+  if (b->seq) (void)hipFree(b->seq);
+  if (b->progress) (void)hipHostFree(b->progress);
   delete b;
 }
 
@@ -584,6 +614,18 @@ int st_batch_create(const st_chunk* chunks, int nchunks, double sigma, double tr
     if (e == hipSuccess) b->owned = true;
   } else if (e == hipSuccess) {
     b->ws = static_cast<char*>(workspace);
+  }
+  if (e == hipSuccess) {
+    what = "hipMalloc (launch counter)";
+    e = hipMalloc(reinterpret_cast<void**>(&b->seq), sizeof(uint64_t));
+    const uint64_t zero = 0;
+    if (e == hipSuccess) e = hipMemcpy(b->seq, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
+    what = "hipHostMalloc (completion record)";
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->progress), b->chunks.size() * sizeof(uint64_t),
+                      hipHostMallocDefault);
+    if (e == hipSuccess) std::memset(b->progress, 0, b->chunks.size() * sizeof(uint64_t));
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -758,7 +800,7 @@ int st_batch_plan(const st_batch* b, int* grouped, int* rounds, int* kernels) {
   if (kernels) {
     int64_t k = 0;
     if (b->grouped) {
-      k = static_cast<int64_t>(b->glaunch.size());
+      for (const GroupLaunch& L : b->glaunch) k += L.kind < 4;
     } else {
       for (const st::host::PathArgs& a : b->chunks) {
         st::host::PathPlan pl;
@@ -768,6 +810,19 @@ int st_batch_plan(const st_batch* b, int* grouped, int* rounds, int* kernels) {
     }
     *kernels = static_cast<int>(k);
   }
+  return ST_OK;
+}
+
+int st_batch_progress(const st_batch* b, uint8_t* done, int nchunks, int64_t* launches) {
+  st::host::clear_error();
+  if (b == nullptr) return fail(ST_ERR_INVALID_ARG, "batch is NULL");
+  if (done != nullptr && nchunks != static_cast<int>(b->chunks.size()))
+    return fail(ST_ERR_INVALID_ARG, "nchunks %d, the batch has %zu chunks", nchunks, b->chunks.size());
+  const uint64_t want = static_cast<uint64_t>(b->launches);
+  if (done != nullptr)
+    for (int c = 0; c < nchunks; ++c)
+      done[c] = want > 0 && __atomic_load_n(b->progress + c, __ATOMIC_ACQUIRE) == want ? 1 : 0;
+  if (launches) *launches = b->launches;
   return ST_OK;
 }
 

@@ -203,6 +203,12 @@ hipError_t launch_grad_fused_grouped(int R, int in_dtype, int rows, const GradFu
 hipError_t launch_strided_grouped(int R, const StridedGroup& p, int64_t blocks, hipStream_t stream);
 hipError_t launch_xfinal_grouped(int R, int lanes, const XFinalGroup& p, int64_t blocks, hipStream_t stream);
 
+// Chunk-batch completion record (k_batch.hip): *seq += 1; and progress[c] = *seq
+// for the `count` chunks c = ids[t] (ids NULL: the one chunk `one`).
+hipError_t launch_batch_begin(uint64_t* seq, hipStream_t stream);
+hipError_t launch_batch_mark(const uint64_t* seq, uint64_t* progress, const int64_t* ids, int count, int64_t one,
+                             hipStream_t stream);
+
 // ---- standalone angles ------------------------------------------------------
 struct AnglesParams {
   const float* e3;

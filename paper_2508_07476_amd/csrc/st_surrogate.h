@@ -39,6 +39,10 @@ struct SgConvParams {
   float* conf;
   int64_t n, nz, ny, nx;
   int64_t x_tiles, y_tiles, zchunk;
+  // z slab: output planes [z_lo, z_hi); `in` holds planes from in_z0 on (the
+  // planes z_lo - 1 .. z_hi, clamped to the volume, must be there), `out` and
+  // `prev` from out_z0 on.  The raw volume and the final outputs are whole.
+  int64_t z_lo, z_hi, in_z0, out_z0;
   int has_axis;
   double center[3];
   double dir[3];

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -110,6 +111,22 @@ FallbackPlan choose_fallback(const TileGrids& g, const std::vector<int>& flags, 
 struct Outputs {
   float *e3, *fa, *ha, *ia;
 };
+
+// Output planes per z slab of the network: as many as let the two activation
+// buffers (a slab plus 4 planes on each side, 64 bytes per voxel) fit in the
+// slab budget (16 GiB, or ST_SURROGATE_SLAB_BYTES), at least one.
+int64_t slab_planes(int64_t nz, int64_t ny, int64_t nx) {
+  size_t budget = size_t(16) << 30;
+  if (const char* v = std::getenv("ST_SURROGATE_SLAB_BYTES")) {
+    char* end = nullptr;
+    const unsigned long long b = std::strtoull(v, &end, 10);
+    if (end != v && *end == '\0' && b > 0) budget = static_cast<size_t>(b);
+  }
+  const size_t plane = static_cast<size_t>(ny) * static_cast<size_t>(nx) * st::kSgChannels * 2;
+  const int64_t halo = 2 * (st::kSgLayers - 1);
+  const int64_t fit = static_cast<int64_t>(budget / (2 * plane));
+  return std::max<int64_t>(1, std::min<int64_t>(nz, fit - halo));
+}
 
 // The structure-tensor path on the whole volume into temporary outputs, then a
 // per-voxel merge where the confidence is below the threshold.
@@ -326,27 +343,37 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
     if (q && (reinterpret_cast<uintptr_t>(q) % 4) != 0)
       return fail(ST_ERR_INVALID_ARG, "weights and float outputs must be 4-byte aligned");
 
-  // ---- workspace: activations, packed weights, confidence, tile flags ----
+  // ---- workspace: activations of one z slab, packed weights, confidence, tile flags ----
   const int C = st::kSgChannels;
-  const size_t act = align256(N * C * 2);
+  const int64_t slab = slab_planes(nz, ny, nx);
+  const size_t act = align256(static_cast<size_t>(std::min<int64_t>(nz, slab + 2 * (st::kSgLayers - 1))) * ny * nx *
+                              C * 2);
   const size_t w1b = align256(32 * 32 * 2);
   const size_t w25b = align256(4 * 27 * static_cast<size_t>(C) * C * 2);
   const bool own_conf = fallback && confidence == nullptr;
   const size_t confb = own_conf ? align256(N * 4) : 0;
   TileGrids grids(nz, ny, nx);
   const size_t flagb = fallback ? align256(grids.total * 4) : 0;
-  const size_t total = 2 * act + w1b + w25b + confb + flagb;
+  const size_t total = w1b + w25b + confb + flagb;
   hipStream_t stream = static_cast<hipStream_t>(stream_);
+  // the activations (the bulk) are released as soon as the head has run, so
+  // that a fallback does not hold them too
+  char* acts = nullptr;
   char* ws = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), total, stream);
-  if (e != hipSuccess || ws == nullptr) {
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&acts), 2 * act, stream);
+  if (e == hipSuccess && acts != nullptr) {
+    e = hipMallocAsync(reinterpret_cast<void**>(&ws), total, stream);
+    if (e != hipSuccess || ws == nullptr) (void)hipFreeAsync(acts, stream);
+  }
+  if (e != hipSuccess || acts == nullptr || ws == nullptr) {
     (void)hipGetLastError();
-    return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) failed: %s", total, hipGetErrorString(e));
+    return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu + %zu) failed: %s", 2 * act, total,
+                hipGetErrorString(e));
   }
   char* q = ws;
   auto take = [&](size_t b) { char* r = b ? q : nullptr; q += b; return r; };
-  __bf16* actA = reinterpret_cast<__bf16*>(take(act));
-  __bf16* actB = reinterpret_cast<__bf16*>(take(act));
+  __bf16* actA = reinterpret_cast<__bf16*>(acts);
+  __bf16* actB = reinterpret_cast<__bf16*>(acts + act);
   __bf16* w1 = reinterpret_cast<__bf16*>(take(w1b));
   __bf16* w25 = reinterpret_cast<__bf16*>(take(w25b));
   float* conf = own_conf ? reinterpret_cast<float*>(take(confb)) : confidence;
@@ -375,17 +402,34 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
     p.has_axis = has_axis;
     if (has_axis)
       for (int i = 0; i < 3; ++i) { p.center[i] = axis_center[i]; p.dir[i] = unit[i]; }
-    const __bf16* in = nullptr;
     __bf16* bufs[2] = {actA, actB};
-    for (int layer = 1; layer <= st::kSgLayers && e == hipSuccess; ++layer) {
-      p.in = in;
-      p.out = layer < st::kSgLayers ? bufs[(layer - 1) & 1] : nullptr;
-      p.w = layer >= 2 ? w25 + static_cast<size_t>(layer - 2) * 27 * C * C : nullptr;
-      p.bias = layer == 1 ? blob + st::kSgOffB1
-                          : blob + st::kSgOffW2 + (layer - 2) * st::kSgLayerStride + C * C * 27;
-      stage = layer == 1 ? "surrogate_conv1" : (layer == st::kSgLayers ? "surrogate_conv5_head" : "surrogate_conv");
-      e = st::host::timed_call(stage, stream, [&] { return st::launch_sg_conv(layer, dtype, p, stream); });
-      in = p.out;
+    // z slabs: for output planes [za, zb), layer l computes the planes within
+    // 5 - l of them (each later layer needs one more plane on each side)
+    for (int64_t za = 0; za < nz && e == hipSuccess; za += slab) {
+      const int64_t zb = std::min(nz, za + slab);
+      const __bf16* in = nullptr;
+      int64_t in_z0 = 0;
+      for (int layer = 1; layer <= st::kSgLayers && e == hipSuccess; ++layer) {
+        const int64_t g = st::kSgLayers - layer;
+        p.z_lo = std::max<int64_t>(0, za - g);
+        p.z_hi = std::min(nz, zb + g);
+        p.in = in;
+        p.in_z0 = in_z0;
+        p.out = layer < st::kSgLayers ? bufs[(layer - 1) & 1] : nullptr;
+        p.out_z0 = p.z_lo;
+        p.w = layer >= 2 ? w25 + static_cast<size_t>(layer - 2) * 27 * C * C : nullptr;
+        p.bias = layer == 1 ? blob + st::kSgOffB1
+                            : blob + st::kSgOffW2 + (layer - 2) * st::kSgLayerStride + C * C * 27;
+        stage = layer == 1 ? "surrogate_conv1" : (layer == st::kSgLayers ? "surrogate_conv5_head" : "surrogate_conv");
+        e = st::host::timed_call(stage, stream, [&] { return st::launch_sg_conv(layer, dtype, p, stream); });
+        in = p.out;
+        in_z0 = p.z_lo;
+      }
+    }
+    if (e == hipSuccess) {
+      stage = "hipFreeAsync";
+      e = hipFreeAsync(acts, stream);
+      acts = nullptr;
     }
     if (e != hipSuccess || !fallback) break;
     // which tiles hold voxels below the threshold (the host needs the answer)
@@ -418,6 +462,7 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
     }
   } while (false);
   hipError_t f = hipFreeAsync(ws, stream);
+  if (acts != nullptr) (void)hipFreeAsync(acts, stream);
   if (status != ST_OK) return status;
   if (e == hipSuccess && f != hipSuccess) { e = f; stage = "hipFreeAsync"; }
   if (e != hipSuccess) return device_fail(e, stage);
@@ -552,6 +597,7 @@ extern "C" int st_surrogate_grad(const void* patches, int dtype, int64_t npatch,
     p.x_tiles = (nx + 31) / 32;
     p.y_tiles = (ny + 7) / 8;
     p.zchunk = 16;
+    p.z_lo = 0; p.z_hi = nz; p.in_z0 = 0; p.out_z0 = 0;  // whole-stack buffers
     for (int layer = 1; layer <= st::kSgLayers && e == hipSuccess; ++layer) {
       p.in = layer == 1 ? nullptr : xact[layer - 1];
       p.out = xact[layer];

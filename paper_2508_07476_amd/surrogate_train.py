@@ -222,6 +222,7 @@ def main(argv=None):
     steps = max(1, int(round(args.epochs * per_epoch)))
     log_every = max(1, steps // 40)
     acc = torch.zeros(8, dtype=torch.float64, device=dev)
+    since = 0
     order = rng.permutation(len(origins))
     pos = 0
     t1 = time.time()
@@ -235,11 +236,13 @@ def main(argv=None):
         warm = min(1.0, step / args.warmup)
         lr = args.lr * warm * 0.5 * (1.0 + math.cos(math.pi * step / steps))
         st.st_surrogate_adam(params, grad, m, v, step, lr)
+        since += 1
         if step % log_every == 0 or step == steps:
-            a = (acc / log_every).cpu().numpy()
+            a = (acc / since).cpu().numpy()
             acc.zero_()
+            since = 0
             print(f"step {step}/{steps}: loss {a[3]:.4f} dir {a[0]:.4f} fa {a[1]:.5f} conf {a[2]:.4f} "
-                  f"within 2 deg {a[5] / max(a[4], 1):.3f} mean angle {math.degrees(a[6]):.2f} deg "
+                  f"within 2 deg {a[5] / max(a[4], 1):.3f} mean angle {a[6]:.2f} deg "
                   f"lr {lr:.2e} ({time.time() - t1:.0f} s)", flush=True)
     torch.cuda.synchronize()
     train_s = time.time() - t1

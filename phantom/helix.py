@@ -88,6 +88,17 @@ def spec_two_annuli_u16(seed: int = 2, shape=(2048, 1024, 1024)) -> PhantomSpec:
                        with_mask=False)
 
 
+def spec_surrogate_u16(seed: int = 3, shape=(1024, 1024, 1024)) -> PhantomSpec:
+    """Surrogate inference volume: one annulus (r in [0.1875, 0.4375] x the
+    in-plane size, 192..448 at 1024), helix +70 deg endo to -50 deg epi (inside
+    the surrogate's training range of +-[30, 80] deg), rod period 5, noise
+    0.02 / 0.06 / 0.12 by z-thirds (inside the training range 0.01..0.2),
+    16-bit quantised, with the annulus mask."""
+    s = max(shape[1], shape[2])
+    return PhantomSpec(shape=tuple(shape), annuli=(Annulus(0.1875 * s, 0.4375 * s, 70.0, -50.0),),
+                       period=5.0, noise=(0.02, 0.06, 0.12), dtype="u16", seed=seed, with_mask=True)
+
+
 def helix_angle(spec: PhantomSpec, r):
     """True helix angle (radians) at cylindrical radius ``r`` (tensor), NaN outside every annulus."""
     r = torch.as_tensor(r, dtype=torch.float64)

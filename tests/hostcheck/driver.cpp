@@ -11,6 +11,8 @@
 // prints "hostcheck: OK" when every call returned what it should; the stub
 // aborts on any broken rule, ASan / UBSan on any memory or undefined-behaviour
 // error.
+#include <string>
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -136,6 +138,16 @@ void surrogate(hipStream_t s) {
              ST_OK, "st_surrogate_infer (e3 only)");
     }
   }
+  // slabs of 3 output planes (11-plane buffers), with and without a fallback
+  setenv("ST_SURROGATE_SLAB_BYTES", std::to_string(2 * 11 * 90 * 150 * 64).c_str(), 1);
+  {
+    Vol c(25, 90, 150, ST_DTYPE_U16, true);
+    for (double minc : {0.0, 0.9})
+      expect(st_surrogate_infer(c.v, c.dtype, c.mask, c.nz, c.ny, c.nx, w, host.size() * 4, minc, 1.0, 2.0, 4.0, kC,
+                                kD, c.e3, c.fa, c.ha, c.ia, c.conf, s),
+             ST_OK, "st_surrogate_infer in slabs");
+  }
+  unsetenv("ST_SURROGATE_SLAB_BYTES");
   // the per-tile fallback: a crop (the last tile flagged), the whole volume
   // (every third or every tile flagged: the crops would cost more), nothing (no
   // tile flagged), and the chains batch for a sigma whose radius needs the
@@ -276,7 +288,17 @@ void batches(hipStream_t s, hipStream_t other) {
   const int n = static_cast<int>(ch.desc.size());
   for (int lanes : {0, 1, 3, ST_BATCH_GROUPED}) {
     st_batch* b = create(ch, lanes);
-    for (int r = 0; r < 3; ++r) expect(st_batch_launch(b, s), ST_OK, "st_batch_launch");
+    {  // completion record: nothing done before the first launch, three launches counted
+      std::vector<uint8_t> done(n, 7);
+      int64_t launches = -1;
+      expect(st_batch_progress(b, done.data(), n, &launches), ST_OK, "st_batch_progress");
+      if (launches != 0 || std::count(done.begin(), done.end(), 0) != n)
+        hc::violation("st_batch_progress before a launch: %lld launches", (long long)launches);
+      for (int r = 0; r < 3; ++r) expect(st_batch_launch(b, s), ST_OK, "st_batch_launch");
+      expect(st_batch_progress(b, nullptr, 0, &launches), ST_OK, "st_batch_progress (count only)");
+      if (launches != 3) hc::violation("st_batch_progress after three launches: %lld", (long long)launches);
+      expect(st_batch_progress(b, done.data(), n + 1, nullptr), ST_ERR_INVALID_ARG, "st_batch_progress size");
+    }
     for (int t = 0; t < 6; ++t) {
       expect(st_batch_tune(b, t % 2 ? s : other, 1 + t % 2), ST_OK, "st_batch_tune");
       int l = 0, g = 0;
@@ -304,6 +326,7 @@ void batches(hipStream_t s, hipStream_t other) {
       std::exit(1);
     }
     expect(st_batch_tiles(b, n, nullptr, nullptr), ST_ERR_INVALID_ARG, "st_batch_tiles out of range");
+    expect(st_batch_progress(nullptr, nullptr, 0, nullptr), ST_ERR_INVALID_ARG, "st_batch_progress of NULL");
     expect(st_batch_tune(b, s, 0), ST_ERR_INVALID_ARG, "st_batch_tune reps 0");
     expect(st_batch_destroy(b), ST_OK, "st_batch_destroy with launches queued");
   }

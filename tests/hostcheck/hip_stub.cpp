@@ -442,8 +442,17 @@ hipError_t hipMallocAsync(void** p, size_t bytes, hipStream_t st) {
   return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 
+// Pinned host memory: the GPU may write it, so it is tracked like a device
+// allocation (kernels' parameters are checked against it) and released with
+// hipHostFree only.
+std::set<void*>& host_allocs() {
+  static std::set<void*>* s = new std::set<void*>();
+  return *s;
+}
+
 hipError_t hipFree(void* p) {
   if (p == nullptr) return hipSuccess;
+  if (host_allocs().count(p)) hc::violation("hipFree of %p, a pinned host allocation (hipHostFree releases it)", p);
   auto it = S().allocs.find(reinterpret_cast<uintptr_t>(p));
   if (it == S().allocs.end()) hc::violation("hipFree of %p, which is not a live stub allocation", p);
   settle_copies();
@@ -456,6 +465,18 @@ hipError_t hipFree(void* p) {
   S().allocs.erase(it);
   std::free(p);
   return hipSuccess;
+}
+
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned int) {
+  *p = new_alloc(bytes);
+  if (*p) host_allocs().insert(*p);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t hipHostFree(void* p) {
+  if (p == nullptr) return hipSuccess;
+  if (!host_allocs().erase(p)) hc::violation("hipHostFree of %p, which is not a live pinned allocation", p);
+  return hipFree(p);
 }
 
 hipError_t hipFreeAsync(void* p, hipStream_t st) {

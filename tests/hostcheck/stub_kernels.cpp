@@ -223,24 +223,46 @@ hipError_t launch_sg_pack(const float* blob, __bf16* w1, __bf16* w25, hipStream_
   return hipSuccess;
 }
 
+namespace {
+// Slab extents of a convolution: the planes it computes must lie in the
+// volume; `in` must hold the planes z_lo - 1 .. z_hi (clamped) from in_z0 on,
+// and `out` / `prev` the planes z_lo .. z_hi - 1 from out_z0 on.
+void check_slab(const SgConvParams& p, bool reads_in, bool writes_out, const char* k) {
+  if (!(0 <= p.z_lo && p.z_lo < p.z_hi && p.z_hi <= p.nz)) hc::violation("%s: planes [%lld, %lld) of %lld", k,
+                                                                         (long long)p.z_lo, (long long)p.z_hi,
+                                                                         (long long)p.nz);
+  const size_t plane = static_cast<size_t>(p.ny * p.nx) * kSgChannels * 2;
+  if (reads_in) {
+    const int64_t lo = std::max<int64_t>(0, p.z_lo - 1), hi = std::min(p.nz, p.z_hi + 1);
+    if (p.in_z0 < 0 || p.in_z0 > lo) hc::violation("%s: input starts at plane %lld, %lld is read", k,
+                                                   (long long)p.in_z0, (long long)lo);
+    hc::need(p.in, static_cast<size_t>(hi - p.in_z0) * plane, "k_sg_conv input activations");
+  }
+  if (writes_out) {
+    if (p.out_z0 < 0 || p.out_z0 > p.z_lo) hc::violation("%s: output starts at plane %lld", k, (long long)p.out_z0);
+    hc::need(p.out, static_cast<size_t>(p.z_hi - p.out_z0) * plane, "k_sg_conv output activations");
+    if (p.prev) hc::need(p.prev, static_cast<size_t>(p.z_hi - p.out_z0) * plane, "k_sg_conv activation mask");
+  }
+  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.z_hi - p.z_lo, p.zchunk), k);
+}
+}  // namespace
+
 hipError_t launch_sg_conv(int layer, int dtype, const SgConvParams& p, hipStream_t stream) {
   const char* k = "k_sg_conv";
   if (layer < 1 || layer > kSgLayers) hc::violation("%s: layer %d", k, layer);
   if (p.n != p.nz * p.ny * p.nx || p.x_tiles != cdiv(p.nx, 32) || p.y_tiles != cdiv(p.ny, 8) || p.zchunk < 1)
     hc::violation("%s: sizes / tiles", k);
   const size_t n = static_cast<size_t>(p.n);
-  const size_t act = n * kSgChannels * 2;
   if (layer == 1) {
     hc::need(p.vol, n * (dtype == ST_DTYPE_U16 ? 2 : 4), "k_sg_conv volume");
     hc::need(p.w1, kSgChannels * 32 * 2, "k_sg_conv first-layer weights");
     hc::need(p.scale_offset, 8, "k_sg_conv input map");
   } else {
-    hc::need(p.in, act, "k_sg_conv input activations");
     hc::need(p.w, 27 * kSgChannels * kSgChannels * 2, "k_sg_conv weights");
   }
+  check_slab(p, layer > 1, layer < kSgLayers, k);
   hc::need(p.bias, kSgChannels * 4, "k_sg_conv bias");
   if (layer < kSgLayers) {
-    hc::need(p.out, act, "k_sg_conv output activations");
     if (p.in && p.in == p.out) hc::violation("%s: layer %d reads and writes one buffer", k, layer);
   } else {
     hc::need(p.head_w, 5 * kSgChannels * 4, "k_sg_conv head weights");
@@ -253,7 +275,6 @@ hipError_t launch_sg_conv(int layer, int dtype, const SgConvParams& p, hipStream
     if (p.conf) hc::need(p.conf, n * 4, "k_sg_conv confidence");
     if ((p.ha || p.ia) && !p.has_axis) hc::violation("%s: angles without an axis", k);
   }
-  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.nz, p.zchunk), k);
   hc::kernel_launch(stream, k);
   return hipSuccess;
 }
@@ -262,31 +283,26 @@ hipError_t launch_sg_conv_hidden(bool first, int dtype, const SgConvParams& p, h
   const char* k = "k_sg_conv (training)";
   if (p.n != p.nz * p.ny * p.nx || p.x_tiles != cdiv(p.nx, 32) || p.y_tiles != cdiv(p.ny, 8) || p.zchunk < 1)
     hc::violation("%s: sizes / tiles", k);
-  const size_t n = static_cast<size_t>(p.n), act = n * kSgChannels * 2;
+  const size_t n = static_cast<size_t>(p.n);
   if (first) {
     hc::need(p.vol, n * (dtype == ST_DTYPE_U16 ? 2 : 4), "k_sg_conv volume");
     hc::need(p.w1, kSgChannels * 32 * 2, "k_sg_conv first-layer weights");
     hc::need(p.scale_offset, 8, "k_sg_conv input map");
   } else {
-    hc::need(p.in, act, "k_sg_conv input activations");
     hc::need(p.w, 27 * kSgChannels * kSgChannels * 2, "k_sg_conv weights");
   }
+  check_slab(p, !first, true, k);
   hc::need(p.bias, kSgChannels * 4, "k_sg_conv bias");
-  hc::need(p.out, act, "k_sg_conv output activations");
-  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.nz, p.zchunk), k);
   hc::kernel_launch(stream, k);
   return hipSuccess;
 }
 
 hipError_t launch_sg_conv_bwd(const SgConvParams& p, hipStream_t stream) {
   const char* k = "k_sg_conv (backward)";
-  const size_t act = static_cast<size_t>(p.n) * kSgChannels * 2;
-  hc::need(p.in, act, "k_sg_conv backward input gradient");
-  hc::need(p.prev, act, "k_sg_conv backward activation mask");
-  hc::need(p.out, act, "k_sg_conv backward output gradient");
+  if (!p.prev) hc::violation("%s: no activation mask", k);
+  check_slab(p, true, true, k);
   hc::need(p.w, 27 * kSgChannels * kSgChannels * 2, "k_sg_conv backward weights");
   if (p.in == p.out || p.prev == p.out) hc::violation("%s: reads and writes one buffer", k);
-  grid_ok(p.x_tiles * p.y_tiles * cdiv(p.nz, p.zchunk), k);
   hc::kernel_launch(stream, k);
   return hipSuccess;
 }
@@ -375,6 +391,32 @@ hipError_t launch_sg_merge(const SgMergeParams& p, hipStream_t stream) {
   if (p.ia) { hc::need(p.ia, n * 4, "k_sg_merge ia"); hc::need(p.pia, n * 4, "k_sg_merge plain ia"); }
   grid_ok(cdiv(p.n, 256), "k_sg_merge");
   hc::kernel_launch(stream, "k_sg_merge");
+  return hipSuccess;
+}
+
+hipError_t launch_batch_begin(uint64_t* seq, hipStream_t stream) {
+  hc::need(seq, 8, "k_batch_begin counter");
+  hc::kernel_launch(stream, "k_batch_begin");
+  return hipSuccess;
+}
+
+hipError_t launch_batch_mark(const uint64_t* seq, uint64_t* progress, const int64_t* ids, int count, int64_t one,
+                             hipStream_t stream) {
+  hc::need(seq, 8, "k_batch_mark counter");
+  if (count < 1) hc::violation("k_batch_mark: %d chunks", count);
+  int64_t top = one;
+  if (ids) {
+    hc::need(ids, static_cast<size_t>(count) * 8, "k_batch_mark chunk ids");
+    top = 0;
+    for (int t = 0; t < count; ++t) {
+      if (ids[t] < 0) hc::violation("k_batch_mark: chunk id %lld", (long long)ids[t]);
+      top = std::max<int64_t>(top, ids[t]);
+    }
+  } else if (count != 1 || one < 0) {
+    hc::violation("k_batch_mark: %d chunks without an id table", count);
+  }
+  hc::need(progress, static_cast<size_t>(top + 1) * 8, "k_batch_mark completion record");
+  hc::kernel_launch(stream, "k_batch_mark");
   return hipSuccess;
 }
 

@@ -180,3 +180,30 @@ def test_batch_graph_replays_are_bitwise_stable(phantom):
         assert _same(_snapshot(b), ref), rep
     assert all(b.tiles(i) == (0, 0) for i in range(len(chunks)))  # untuned: library defaults
     b.close()
+
+
+def test_batch_completion_record(phantom):
+    """The completion record (read without waiting for the GPU): no chunk is
+    done before the first launch, every chunk once a launch has finished, and
+    the launch count follows the launches (the tuner's timing runs included),
+    for chains and grouped launches."""
+    chunks = _chunks(phantom)
+    for lanes in (0, st.ST_BATCH_GROUPED):
+        b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
+                     outputs=OUTS, lanes=lanes)
+        _log("case: completion record, lanes", lanes)
+        done, launches = b.progress()
+        assert launches == 0 and not any(done)
+        b.launch()
+        torch.cuda.synchronize()
+        done, launches = b.progress()
+        assert launches == 1 and all(done), done
+        b.tune(reps=1)  # its timing runs are launches too, and leave every chunk complete
+        done, tuned = b.progress()
+        assert tuned > 1 and all(done), (tuned, done)
+        for _ in range(2):
+            b.launch()
+        torch.cuda.synchronize()
+        done, launches = b.progress()
+        assert launches == tuned + 2 and all(done), (launches, done)
+        b.close()

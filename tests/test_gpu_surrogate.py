@@ -219,3 +219,22 @@ def test_surrogate_is_deterministic():
     torch.cuda.synchronize()
     for k in a:
         assert torch.equal(a[k], b[k]), k
+
+
+def test_surrogate_slabs_give_the_same_bits(monkeypatch):
+    """Thin z slabs (3 output planes, forced through ST_SURROGATE_SLAB_BYTES)
+    give exactly the outputs of one pass over the whole volume: every voxel is
+    computed from the same inputs in the same order."""
+    vol, mask, blob, center, direction, origin = _inputs((24, 40, 70), "u16", True, 12)
+    cl = [center[d] - origin[d] for d in range(3)]
+    v, m, w = vol.to(DEV), mask.to(DEV), torch.from_numpy(blob).to(DEV)
+    outs = ("e3", "fa", "ha", "ia", "confidence")
+    kw = dict(mask=m, axis_center=cl, axis_direction=direction, outputs=outs)
+    whole = st.st_surrogate_infer(v, w, 0.0, **kw)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("ST_SURROGATE_SLAB_BYTES", str(2 * 11 * 40 * 70 * 64))
+    _log("case: surrogate in 3-plane slabs")
+    slabs = st.st_surrogate_infer(v, w, 0.0, **kw)
+    torch.cuda.synchronize()
+    for k in outs:
+        assert torch.equal(whole[k], slabs[k]), k
