@@ -203,11 +203,11 @@ int st_angles(const float* e3, const uint8_t* mask,
  * computing only the planes the next one needs.  Results do not depend on the
  * slab thickness (bit for bit).
  * Device workspace: the two activation buffers, taken with hipMallocAsync on
- * `stream` and released the same way once the network has run (before any
- * fallback); with a fallback, the
- * crops (hipMalloc, about 75 bytes per crop voxel and their batch) or the
- * whole-volume path (hipMallocAsync, st_compute's workspace plus 24 bytes per
- * voxel).
+ * `stream` and released the same way at the end of the call; with a fallback,
+ * the crops (hipMalloc, about 75 bytes per crop voxel and their batch) or,
+ * for the whole volume, nothing more: the structure-tensor path streams z
+ * slabs (each with the path's reach of context, so bit for bit as one pass)
+ * through the activation buffers.
  */
 #define ST_SURROGATE_WEIGHTS 111783
 int st_surrogate_infer(const void* volume, int dtype, const uint8_t* mask,
@@ -230,7 +230,8 @@ int st_surrogate_fallback_info(int* mode, int* tile_edge, int64_t* tiles, int64_
  * (unit) and label FA f:
  *   l_dir = 1 - (u . t)^2;  l_fa = (sigmoid(h[3]) - f)^2;
  *   l_conf = softplus(h[4]) - c h[4], c = [angle(u, t) < 2 degrees] (a target);
- *   L = sum w (l_dir + l_fa + 0.1 l_conf) / sum w.
+ *   L = sum w (l_dir + l_fa + conf_weight l_conf) / sum w  (conf_weight >= 0,
+ *   finite; 0.1 is the trainer's default).
  * Training stores every activation in bf16 (the fifth layer's too, which
  * inference keeps in float32) and every gradient at a pre-activation in bf16;
  * weights enter both passes rounded to bf16 and are kept in float32.
@@ -256,7 +257,7 @@ int st_surrogate_fallback_info(int* mode, int* tile_edge, int64_t* tiles, int64_
 size_t st_surrogate_grad_workspace_bytes(int64_t npatch, int64_t patch);
 int st_surrogate_grad(const void* patches, int dtype, int64_t npatch, int64_t patch,
                       const float* target_e3, const float* target_fa, const uint8_t* weight,
-                      const float* params, float* grad, float* stats,
+                      const float* params, double conf_weight, float* grad, float* stats,
                       void* workspace, size_t workspace_bytes, void* stream);
 int st_surrogate_adam(float* params, const float* grad, float* adam_m, float* adam_v, int64_t step,
                       double lr, double beta1, double beta2, double eps, void* stream);

@@ -137,7 +137,7 @@ def forward(volume, blob, mask=None):
 #   l_dir  = 1 - (u . t)^2                      (invariant under u -> -u, t -> -t)
 #   l_fa   = (sigmoid(h[3]) - f)^2
 #   l_conf = softplus(h[4]) - c h[4],  c = [angle(u, t) < CONF_DEG]  (c is a target, not differentiated)
-#   L = sum_v w (l_dir + l_fa + W_CONF l_conf) / sum_v w
+#   L = sum_v w (l_dir + l_fa + conf_weight l_conf) / sum_v w   (W_CONF by default)
 # Training rounds every stored activation to bf16, x_5 included (inference
 # keeps x_5 in float32), and the backward pass rounds each stored gradient
 # dL/d(pre-activation) to bf16; the weights enter both passes rounded to bf16
@@ -171,7 +171,7 @@ def conv3x3x3_backward(g, x, w):
     return dx, dw, g2.sum(axis=1)
 
 
-def train_loss_grad(blob, patches, target_e3, target_fa, weight, round_bf16=True):
+def train_loss_grad(blob, patches, target_e3, target_fa, weight, round_bf16=True, conf_weight=W_CONF):
     """Training objective (see above) over patches (B, P, P, P) of raw
     intensities, with label directions target_e3 (B, 3, P, P, P), label FA
     (B, P, P, P) and loss weights (B, P, P, P).  Each patch is its own volume.
@@ -212,7 +212,7 @@ def train_loss_grad(blob, patches, target_e3, target_fa, weight, round_bf16=True
         dh = np.empty_like(h)
         dh[:3] = wt * (-2.0 * dot) * (t - dot * u) / safe
         dh[3] = wt * 2.0 * (s3 - target_fa[b]) * s3 * (1.0 - s3)
-        dh[4] = wt * W_CONF * (sigmoid(h[4]) - c)
+        dh[4] = wt * conf_weight * (sigmoid(h[4]) - c)
         grad["Wh"] += np.einsum("ozyx,czyx->oc", dh, x5)
         grad["bh"] += dh.sum(axis=(1, 2, 3))
         g = r(np.einsum("oc,ozyx->czyx", w["Wh"], dh) * (x5 > 0))
@@ -228,5 +228,5 @@ def train_loss_grad(blob, patches, target_e3, target_fa, weight, round_bf16=True
         flat += [grad[f"W{layer}"].ravel() / ws, grad[f"b{layer}"] / ws]
     flat += [grad["Wh"].ravel() / ws, grad["bh"] / ws]
     return {"loss_dir": tot["dir"] / ws, "loss_fa": tot["fa"] / ws, "loss_conf": tot["conf"] / ws,
-            "loss": (tot["dir"] + tot["fa"] + W_CONF * tot["conf"]) / ws, "wsum": tot["wsum"],
+            "loss": (tot["dir"] + tot["fa"] + conf_weight * tot["conf"]) / ws, "wsum": tot["wsum"],
             "within": tot["within"], "grad": np.concatenate(flat)}

@@ -58,7 +58,7 @@ SIGNATURES = {
     "st_surrogate_infer": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _SZ, _D,
                                           _D, _D, _D, _DP, _DP, _P, _P, _P, _P, _P, _P]),
     "st_surrogate_grad_workspace_bytes": (_SZ, [_I64, _I64]),
-    "st_surrogate_grad": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_surrogate_grad": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _D, _P, _P, _P, _SZ, _P]),
     "st_surrogate_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _D, _D, _D, _D, _P]),
     "st_surrogate_fallback_info": (ctypes.c_int, [_P, _P, _P, _P]),
     "st_batch_workspace_bytes": (_SZ, [ctypes.POINTER(StChunk), ctypes.c_int, ctypes.c_int]),
@@ -334,11 +334,13 @@ def st_surrogate_infer(volume, weights, min_confidence: float = 0.0, sigma: floa
     return res
 
 
-def st_surrogate_grad(patches, target_e3, target_fa, weight, params, grad=None, stats=None, workspace=None):
+def st_surrogate_grad(patches, target_e3, target_fa, weight, params, grad=None, stats=None, workspace=None,
+                      conf_weight: float = 0.1):
     """Gradient of the surrogate's training objective (see include/st.h) for a
     stack of patches (npatch * P, P, P) uint16/float32 CUDA tensor, P <= 32.
     target_e3 (3, npatch * P, P, P), target_fa (npatch * P, P, P) float32,
     weight (npatch * P, P, P) uint8/bool, params float32[ST_SURROGATE_WEIGHTS].
+    conf_weight: weight of the confidence term of the objective.
     Returns (grad, stats) float32 CUDA tensors (stats: 8 values)."""
     import torch
     lib = load_library()
@@ -366,7 +368,8 @@ def st_surrogate_grad(patches, target_e3, target_fa, weight, params, grad=None, 
     with torch.cuda.device(dev):
         code = lib.st_surrogate_grad(_ptr(patches), ST_DTYPE_U16 if patches.dtype == torch.uint16 else ST_DTYPE_F32,
                                      npatch, P, _ptr(target_e3), _ptr(target_fa), _ptr(weight), _ptr(params),
-                                     _ptr(grad), _ptr(stats), ws_ptr, ws_bytes, _stream_handle(dev))
+                                     float(conf_weight), _ptr(grad), _ptr(stats), ws_ptr, ws_bytes,
+                                     _stream_handle(dev))
     _check(code)
     return grad, stats
 

@@ -444,14 +444,15 @@ hipError_t launch_conv_ws(const SgConvParams& p, hipStream_t stream) {
 // Voxels inside the mask whose confidence is below the threshold take the
 // structure-tensor path's outputs.
 __global__ void k_sg_merge(const SgMergeParams p) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= p.count) return;
+  const int64_t i = p.begin + t, j = i - p.src_shift;
   if (p.mask != nullptr && p.mask[i] == 0) return;
   if (!(p.conf[i] < p.threshold)) return;
-  if (p.e3) { p.e3[i] = p.pe3[i]; p.e3[p.n + i] = p.pe3[p.n + i]; p.e3[2 * p.n + i] = p.pe3[2 * p.n + i]; }
-  if (p.fa) p.fa[i] = p.pfa[i];
-  if (p.ha) p.ha[i] = p.pha[i];
-  if (p.ia) p.ia[i] = p.pia[i];
+  if (p.e3) { p.e3[i] = p.pe3[j]; p.e3[p.n + i] = p.pe3[p.src_n + j]; p.e3[2 * p.n + i] = p.pe3[2 * p.src_n + j]; }
+  if (p.fa) p.fa[i] = p.pfa[j];
+  if (p.ha) p.ha[i] = p.pha[j];
+  if (p.ia) p.ia[i] = p.pia[j];
 }
 
 template <bool FIRST, bool BWD = false>
@@ -489,7 +490,8 @@ hipError_t launch_sg_conv_bwd(const SgConvParams& p, hipStream_t stream) {
 }
 
 hipError_t launch_sg_merge(const SgMergeParams& p, hipStream_t stream) {
-  hipLaunchKernelGGL(k_sg_merge, dim3(static_cast<unsigned>((p.n + 255) / 256)), dim3(256), 0, stream, p);
+  if (p.count < 1 || (p.count + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sg_merge, dim3(static_cast<unsigned>((p.count + 255) / 256)), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
 

@@ -20,7 +20,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int C = kSgChannels;
 constexpr int WX = kSgTrainMaxX;   // voxels of a staged row
-constexpr float kWConf = 0.1f;     // weight of the confidence term
 constexpr float kConfDeg = 2.0f;   // confidence target: within this angle of the label
 
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
@@ -93,7 +92,7 @@ __global__ __launch_bounds__(256) void k_sg_head_train(const SgHeadParams p) {
         const float ang = atan2f(sqrtf(cz * cz + cy * cy + cx * cx), fabsf(dot)) * 57.29577951308232f;
         const float c = ang < kConfDeg ? 1.f : 0.f;
         const float s4 = 1.f / (1.f + expf(-h[4]));
-        d[4] = kWConf * (s4 - c);
+        d[4] = p.w_conf * (s4 - c);
         d[5] = l_dir;
         d[6] = e * e;
         d[7] = fmaxf(h[4], 0.f) + log1pf(expf(-fabsf(h[4]))) - c * h[4];
@@ -318,7 +317,7 @@ __global__ void k_sg_finish(float* grad, int64_t n, const float* raw) {
     grad[i] = i < 2 ? 0.f : grad[i] * inv;
 }
 
-__global__ void k_sg_stats(const float* raw, float* stats) {
+__global__ void k_sg_stats(const float* raw, float w_conf, float* stats) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const float wsum = raw[3];
   const float inv = wsum > 0.f ? 1.f / wsum : 0.f;
@@ -326,7 +325,7 @@ __global__ void k_sg_stats(const float* raw, float* stats) {
   stats[0] = dir;
   stats[1] = fa;
   stats[2] = conf;
-  stats[3] = dir + fa + kWConf * conf;
+  stats[3] = dir + fa + w_conf * conf;
   stats[4] = wsum;
   stats[5] = raw[4];
   stats[6] = raw[5] * inv;
@@ -379,11 +378,11 @@ hipError_t launch_sg_reduce(const float* partial, int blocks, int len, int mode,
   return hipGetLastError();
 }
 
-hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float* stats, hipStream_t stream) {
+hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float w_conf, float* stats, hipStream_t stream) {
   hipLaunchKernelGGL(k_sg_finish, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, grad, n, raw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sg_stats, dim3(1), dim3(64), 0, stream, raw, stats);
+  hipLaunchKernelGGL(k_sg_stats, dim3(1), dim3(64), 0, stream, raw, w_conf, stats);
   return hipGetLastError();
 }
 

@@ -48,6 +48,10 @@ struct SgConvParams {
   double dir[3];
 };
 
+// Merge of a run of voxels [begin, begin + count) of the volume (n voxels):
+// where the mask holds and the confidence is below the threshold, the outputs
+// take the structure-tensor path's, read at voxel i - src_shift of a source of
+// src_n voxels (e3 planes src_n apart).
 struct SgMergeParams {
   const uint8_t* mask;
   const float* conf;
@@ -61,6 +65,7 @@ struct SgMergeParams {
   float* ha;
   float* ia;
   int64_t n;
+  int64_t begin, count, src_shift, src_n;
 };
 
 hipError_t launch_sg_pack(const float* blob, __bf16* w1, __bf16* w25, hipStream_t stream);
@@ -156,6 +161,7 @@ struct SgHeadParams {
   __bf16* g5;             // [N][32]: (Wh^T dL/dh) * (x5 > 0), unnormalised
   float* partial;         // [blocks][kSgHeadSums]
   int64_t n;
+  float w_conf;           // weight of the confidence term
 };
 hipError_t launch_sg_head_train(const SgHeadParams& p, int blocks, hipStream_t stream);
 
@@ -180,7 +186,7 @@ hipError_t launch_sg_reduce(const float* partial, int blocks, int len, int mode,
 // trained); raw = the six loss sums (dir, fa, conf, weights, within, angle);
 // stats[0..7] = mean dir, fa, conf terms, total loss, sum of weights, voxels
 // within 2 degrees, mean angle (degrees), sum of weights.
-hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float* stats, hipStream_t stream);
+hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float w_conf, float* stats, hipStream_t stream);
 // Adam on float32 parameters (moments m, v; step >= 1), skipping the first `frozen` values.
 hipError_t launch_sg_adam(float* params, const float* grad, float* m, float* v, int64_t n, int64_t frozen,
                           int64_t step, float lr, float beta1, float beta2, float eps, hipStream_t stream);

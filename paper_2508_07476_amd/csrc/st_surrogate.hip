@@ -128,36 +128,70 @@ int64_t slab_planes(int64_t nz, int64_t ny, int64_t nx) {
   return std::max<int64_t>(1, std::min<int64_t>(nz, fit - halo));
 }
 
-// The structure-tensor path on the whole volume into temporary outputs, then a
-// per-voxel merge where the confidence is below the threshold.
+// The structure-tensor path over the whole volume, streamed in z slabs through
+// `scratch` (the network's activation buffers, no longer needed): each slab's
+// planes plus the path's reach on both sides (a contiguous sub-volume, whose
+// interior planes come out bit for bit as in one pass over the volume) into
+// temporary outputs, then a merge of the slab's own planes where the
+// confidence is below the threshold.  One pass when the whole volume fits; a
+// buffer of its own when the scratch cannot hold a useful slab.
 int whole_fallback(const void* volume, int dtype, const uint8_t* mask, int64_t nz, int64_t ny, int64_t nx,
                    double sigma, double rho, double truncate, const double* axis_center,
                    const double* axis_direction, const float* conf, float threshold, const Outputs& o,
-                   hipStream_t stream) {
-  const size_t N = static_cast<size_t>(nz * ny * nx);
-  const size_t plainw = st::host::path_workspace_bytes(nz, ny, nx);
-  if (plainw == 0) return fail(ST_ERR_INVALID_ARG, "workspace size of the volume overflows");
-  const size_t pe3b = o.e3 ? align256(3 * N * 4) : 0, pfab = o.fa ? align256(N * 4) : 0;
-  const size_t phab = o.ha ? align256(N * 4) : 0, piab = o.ia ? align256(N * 4) : 0;
-  const size_t total = align256(plainw) + pe3b + pfab + phab + piab;
-  char* ws = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), total, stream);
-  if (e != hipSuccess || ws == nullptr) {
-    (void)hipGetLastError();
-    return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) failed: %s", total, hipGetErrorString(e));
+                   char* scratch, size_t scratch_bytes, hipStream_t stream) {
+  const size_t plane = static_cast<size_t>(ny) * static_cast<size_t>(nx);
+  const size_t esz = dtype == ST_DTYPE_U16 ? 2 : 4;
+  const int halo = st::host::path_halo(sigma, rho, truncate);
+  // bytes for a sub-volume of P planes: the path's workspace and the temporary outputs
+  auto need = [&](int64_t P) -> size_t {
+    const size_t w = st::host::path_workspace_bytes(P, ny, nx);
+    if (w == 0) return SIZE_MAX;
+    const size_t v = static_cast<size_t>(P) * plane;
+    return align256(w) + (o.e3 ? align256(3 * v * 4) : 0) + (o.fa ? align256(v * 4) : 0) +
+           (o.ha ? align256(v * 4) : 0) + (o.ia ? align256(v * 4) : 0);
+  };
+  int64_t P = 0;  // the most planes the scratch holds
+  for (int64_t lo = 1, hi = nz; lo <= hi;) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (need(mid) <= scratch_bytes) { P = mid; lo = mid + 1; } else { hi = mid - 1; }
   }
-  char* q = ws;
+  int64_t S = P == nz ? nz : P - 2 * static_cast<int64_t>(halo);  // output planes per slab
+  char* base = scratch;
+  char* own = nullptr;
+  if (S < 16 && S < nz) {  // too thin to be worth it: a buffer of slabs of 64 planes
+    P = std::min<int64_t>(nz, 64 + 2 * static_cast<int64_t>(halo));
+    S = P == nz ? nz : 64;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&own), need(P), stream);
+    if (e != hipSuccess || own == nullptr) {
+      (void)hipGetLastError();
+      return fail(ST_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) failed: %s", need(P), hipGetErrorString(e));
+    }
+    base = own;
+  }
+  const size_t vP = static_cast<size_t>(P) * plane;
+  char* q = base;
   auto take = [&](size_t b) { char* r = b ? q : nullptr; q += b; return r; };
-  char* pws = take(align256(plainw));
-  float* pe3 = reinterpret_cast<float*>(take(pe3b));
-  float* pfa = reinterpret_cast<float*>(take(pfab));
-  float* pha = reinterpret_cast<float*>(take(phab));
-  float* pia = reinterpret_cast<float*>(take(piab));
+  char* pws = take(align256(st::host::path_workspace_bytes(P, ny, nx)));
+  float* pe3 = reinterpret_cast<float*>(take(o.e3 ? align256(3 * vP * 4) : 0));
+  float* pfa = reinterpret_cast<float*>(take(o.fa ? align256(vP * 4) : 0));
+  float* pha = reinterpret_cast<float*>(take(o.ha ? align256(vP * 4) : 0));
+  float* pia = reinterpret_cast<float*>(take(o.ia ? align256(vP * 4) : 0));
   const char* stage = "fallback arguments";
-  do {
+  hipError_t e = hipSuccess;
+  for (int64_t za = 0; za < nz && e == hipSuccess; za += S) {
+    const int64_t zb = std::min(nz, za + S);
+    const int64_t a = S == nz ? 0 : std::max<int64_t>(0, za - halo), b = S == nz ? nz : std::min(nz, zb + halo);
+    double center[3];
+    if (axis_center) {
+      center[0] = axis_center[0] - static_cast<double>(a);
+      center[1] = axis_center[1];
+      center[2] = axis_center[2];
+    }
     st::host::PathArgs pa;
-    if (st::host::prepare_path(pa, volume, dtype, mask, nz, ny, nx, sigma, rho, truncate, axis_center,
-                               axis_direction, pe3, nullptr, pfa, pha, pia, nullptr) != ST_OK) {
+    if (st::host::prepare_path(pa, static_cast<const char*>(volume) + static_cast<size_t>(a) * plane * esz, dtype,
+                               mask ? mask + static_cast<size_t>(a) * plane : nullptr, b - a, ny, nx, sigma, rho,
+                               truncate, axis_center ? center : nullptr, axis_direction, pe3, nullptr, pfa, pha, pia,
+                               nullptr) != ST_OK) {
       e = hipErrorInvalidValue;  // cannot happen: every argument was validated
       break;
     }
@@ -166,11 +200,16 @@ int whole_fallback(const void* volume, int dtype, const uint8_t* mask, int64_t n
     st::SgMergeParams m;
     m.mask = mask; m.conf = conf; m.threshold = threshold;
     m.pe3 = pe3; m.pfa = pfa; m.pha = pha; m.pia = pia;
-    m.e3 = o.e3; m.fa = o.fa; m.ha = o.ha; m.ia = o.ia; m.n = static_cast<int64_t>(N);
+    m.e3 = o.e3; m.fa = o.fa; m.ha = o.ha; m.ia = o.ia;
+    m.n = nz * static_cast<int64_t>(plane);
+    m.begin = za * static_cast<int64_t>(plane);
+    m.count = (zb - za) * static_cast<int64_t>(plane);
+    m.src_shift = a * static_cast<int64_t>(plane);
+    m.src_n = (b - a) * static_cast<int64_t>(plane);
     stage = "surrogate_merge";
     e = st::host::timed_call(stage, stream, [&] { return st::launch_sg_merge(m, stream); });
-  } while (false);
-  hipError_t f = hipFreeAsync(ws, stream);
+  }
+  hipError_t f = own ? hipFreeAsync(own, stream) : hipSuccess;
   if (e == hipSuccess && f != hipSuccess) { e = f; stage = "hipFreeAsync"; }
   return e == hipSuccess ? ST_OK : device_fail(e, stage);
 }
@@ -356,8 +395,7 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
   const size_t flagb = fallback ? align256(grids.total * 4) : 0;
   const size_t total = w1b + w25b + confb + flagb;
   hipStream_t stream = static_cast<hipStream_t>(stream_);
-  // the activations (the bulk) are released as soon as the head has run, so
-  // that a fallback does not hold them too
+  // the activations (the bulk) serve a whole-volume fallback as its scratch
   char* acts = nullptr;
   char* ws = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&acts), 2 * act, stream);
@@ -426,11 +464,6 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
         in_z0 = p.z_lo;
       }
     }
-    if (e == hipSuccess) {
-      stage = "hipFreeAsync";
-      e = hipFreeAsync(acts, stream);
-      acts = nullptr;
-    }
     if (e != hipSuccess || !fallback) break;
     // which tiles hold voxels below the threshold (the host needs the answer)
     st::SgTileFlagParams fp;
@@ -455,7 +488,7 @@ extern "C" int st_surrogate_infer(const void* volume, int dtype, const uint8_t* 
     Outputs out{e3, fa, ha, ia};
     if (plan.mode == 2) {
       status = whole_fallback(volume, dtype, mask, nz, ny, nx, sigma, rho, truncate, axis_center, axis_direction,
-                              conf, static_cast<float>(min_confidence), out, stream);
+                              conf, static_cast<float>(min_confidence), out, acts, 2 * act, stream);
     } else {
       status = tile_fallback(plan, volume, dtype, mask, nz, ny, nx, sigma, rho, truncate, axis_center,
                              axis_direction, conf, static_cast<float>(min_confidence), out, stream);
@@ -515,12 +548,14 @@ extern "C" size_t st_surrogate_grad_workspace_bytes(int64_t npatch, int64_t patc
 
 extern "C" int st_surrogate_grad(const void* patches, int dtype, int64_t npatch, int64_t patch,
                                  const float* target_e3, const float* target_fa, const uint8_t* weight,
-                                 const float* params, float* grad, float* stats, void* workspace,
-                                 size_t workspace_bytes, void* stream_) {
+                                 const float* params, double conf_weight, float* grad, float* stats,
+                                 void* workspace, size_t workspace_bytes, void* stream_) {
   st::host::clear_error();
   if (patches == nullptr || target_e3 == nullptr || target_fa == nullptr || weight == nullptr ||
       params == nullptr || grad == nullptr || stats == nullptr)
     return fail(ST_ERR_INVALID_ARG, "st_surrogate_grad: a required pointer is NULL");
+  if (!std::isfinite(conf_weight) || conf_weight < 0.0)
+    return fail(ST_ERR_INVALID_ARG, "conf_weight must be finite and >= 0");
   if (dtype != ST_DTYPE_U16 && dtype != ST_DTYPE_F32)
     return fail(ST_ERR_INVALID_ARG, "dtype %d is neither ST_DTYPE_U16 nor ST_DTYPE_F32", dtype);
   TrainPlan t;
@@ -618,6 +653,7 @@ extern "C" int st_surrogate_grad(const void* patches, int dtype, int64_t npatch,
     h.g5 = gbuf[0];
     h.partial = hpart;
     h.n = t.n;
+    h.w_conf = static_cast<float>(conf_weight);
     stage = "surrogate_train_head";
     if ((e = st::launch_sg_head_train(h, t.head_blocks, stream)) != hipSuccess) break;
     stage = "surrogate_train_reduce";
@@ -659,7 +695,8 @@ extern "C" int st_surrogate_grad(const void* patches, int dtype, int64_t npatch,
     // the head gradient (Wh, bh) into place; everything divided by the weight sum
     if ((e = st::launch_sg_reduce(sums, 1, 5 * C + 5, 0, grad + st::kSgOffHead, stream)) != hipSuccess) break;
     stage = "surrogate_train_finish";
-    e = st::launch_sg_finish(grad, ST_SURROGATE_WEIGHTS, sums + 5 * C + 5, stats, stream);
+    e = st::launch_sg_finish(grad, ST_SURROGATE_WEIGHTS, sums + 5 * C + 5, static_cast<float>(conf_weight), stats,
+                             stream);
   } while (false);
   if (owned) {
     hipError_t f = hipFreeAsync(ws, stream);

@@ -9,9 +9,10 @@ convolutions with 32 channels, ReLU and clamped faces, then a 1x1x1 head with
 five outputs (fibre vector, FA logit, confidence logit).  The objective
 (include/st.h, st_surrogate_grad) is
 
-  mean(1 - (u . t)^2) + mean((sigmoid(h3) - FA_t)^2) + 0.1 BCE(h4, [angle(u, t) < 2 deg])
+  mean(1 - (u . t)^2) + mean((sigmoid(h3) - FA_t)^2) + w_c BCE(h4, [angle(u, t) < 2 deg])
 
-over the weighted voxels, u = h[0:3] / |h[0:3]|, t the label's unit vector.
+over the weighted voxels, u = h[0:3] / |h[0:3]|, t the label's unit vector,
+w_c the confidence term's weight (--conf-weight, 0.1 by default).
 
 Data: rod-lattice helical phantoms whose helix range, rod period and noise are
 drawn per volume (helix angles of +-[30, 80] degrees across the wall, period
@@ -176,6 +177,14 @@ def evaluate(torch, st, helix, blob, count, shape, sigma, rho, seed, dev, thresh
         keep = conf >= thr
         res[f"fallback_{thr}"] = float(1.0 - keep.mean())
         res[f"median_deg_conf_{thr}"] = float(np.median(ang[keep])) if keep.any() else float("nan")
+    # reliability: per confidence bin, its share of the voxels and the share of
+    # them within 2 degrees (a calibrated head has the second near the bin's value)
+    edges = [0.0, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0001]
+    res["reliability"] = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (conf >= lo) & (conf < hi)
+        res["reliability"].append({"conf": [lo, min(hi, 1.0)], "share": round(float(sel.mean()), 4),
+                                   "within_2deg": round(float((ang[sel] < 2.0).mean()), 4) if sel.any() else None})
     return res
 
 
@@ -192,6 +201,7 @@ def main(argv=None):
     ap.add_argument("--rho", type=float, default=2.0)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--conf-weight", type=float, default=0.1, help="weight of the confidence term")
     ap.add_argument("--min-weight", type=int, default=2000)
     ap.add_argument("--eval-volumes", type=int, default=4)
     ap.add_argument("--seed", type=int, default=7)
@@ -231,7 +241,7 @@ def main(argv=None):
             order, pos = rng.permutation(len(origins)), 0
         vol, e3, fa, w = gather(origins[order[pos:pos + args.batch]])
         pos += args.batch
-        st.st_surrogate_grad(vol, e3, fa, w, params, grad=grad, stats=stats, workspace=ws)
+        st.st_surrogate_grad(vol, e3, fa, w, params, grad=grad, stats=stats, workspace=ws, conf_weight=args.conf_weight)
         acc += stats.double()
         warm = min(1.0, step / args.warmup)
         lr = args.lr * warm * 0.5 * (1.0 + math.cos(math.pi * step / steps))
@@ -253,6 +263,7 @@ def main(argv=None):
             "epochs": args.epochs, "steps": steps, "batch": args.batch, "patch": args.patch,
             "volumes": args.volumes, "shape": list(shape), "sigma": args.sigma, "rho": args.rho,
             "lr": args.lr, "warmup": args.warmup, "min_weight": args.min_weight, "seed": args.seed,
+            "conf_weight": args.conf_weight,
             "in_scale": IN_SCALE, "in_offset": IN_OFFSET, "values": int(out.size),
             "train_seconds": round(train_s, 1), "ms_per_step": round(1e3 * train_s / steps, 3),
             "held_out": {"volumes": args.eval_volumes, "seed": args.seed + 1000, **ev},

@@ -147,6 +147,20 @@ void surrogate(hipStream_t s) {
                                 kD, c.e3, c.fa, c.ha, c.ia, c.conf, s),
              ST_OK, "st_surrogate_infer in slabs");
   }
+  // a whole-volume fallback streamed in slabs through the activation buffers
+  // (28-plane buffers of 40 x 60 planes: about 49 planes of the path per slab)
+  setenv("ST_SURROGATE_SLAB_BYTES", std::to_string(2 * 28 * 40 * 60 * 64).c_str(), 1);
+  setenv("HOSTCHECK_FLAGS", "all", 1);
+  {
+    Vol c(80, 40, 60, ST_DTYPE_F32, true);
+    expect(st_surrogate_infer(c.v, c.dtype, c.mask, c.nz, c.ny, c.nx, w, host.size() * 4, 0.9, 1.0, 2.0, 4.0, kC, kD,
+                              c.e3, c.fa, c.ha, c.ia, c.conf, s),
+           ST_OK, "st_surrogate_infer with a streamed whole-volume fallback");
+    int mode = -1;
+    expect(st_surrogate_fallback_info(&mode, nullptr, nullptr, nullptr), ST_OK, "st_surrogate_fallback_info");
+    if (mode != 2) hc::violation("streamed fallback: mode %d", mode);
+  }
+  unsetenv("HOSTCHECK_FLAGS");
   unsetenv("ST_SURROGATE_SLAB_BYTES");
   // the per-tile fallback: a crop (the last tile flagged), the whole volume
   // (every third or every tile flagged: the crops would cost more), nothing (no
@@ -189,13 +203,16 @@ void training(hipStream_t s) {
     const size_t wsb = st_surrogate_grad_workspace_bytes(npatch, P);
     void* ws = dev(wsb);
     for (int step = 1; step <= 2; ++step) {
-      expect(st_surrogate_grad(vol, ST_DTYPE_U16, npatch, P, t, fa, w, params, grad, stats, step == 1 ? ws : nullptr,
+      expect(st_surrogate_grad(vol, ST_DTYPE_U16, npatch, P, t, fa, w, params, 0.1 * step, grad, stats,
+                               step == 1 ? ws : nullptr,
                                step == 1 ? wsb : 0, s),
              ST_OK, "st_surrogate_grad");
       expect(st_surrogate_adam(params, grad, m, v, step, 1e-3, 0.9, 0.999, 1e-8, s), ST_OK, "st_surrogate_adam");
     }
-    expect(st_surrogate_grad(vol, ST_DTYPE_U16, npatch, 33, t, fa, w, params, grad, stats, nullptr, 0, s),
+    expect(st_surrogate_grad(vol, ST_DTYPE_U16, npatch, 33, t, fa, w, params, 0.1, grad, stats, nullptr, 0, s),
            ST_ERR_INVALID_ARG, "st_surrogate_grad with 33-voxel patches");
+    expect(st_surrogate_grad(vol, ST_DTYPE_U16, npatch, P, t, fa, w, params, -1.0, grad, stats, nullptr, 0, s),
+           ST_ERR_INVALID_ARG, "st_surrogate_grad with a negative confidence weight");
     expect(st_surrogate_adam(params, grad, m, v, 0, 1e-3, 0.9, 0.999, 1e-8, s), ST_ERR_INVALID_ARG,
            "st_surrogate_adam step 0");
     for (void* q : {vol, (void*)t, (void*)fa, (void*)w, (void*)params, (void*)grad, (void*)m, (void*)v, (void*)stats,

@@ -362,7 +362,8 @@ hipError_t launch_sg_reduce(const float* partial, int blocks, int len, int mode,
   return hipSuccess;
 }
 
-hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float* stats, hipStream_t stream) {
+hipError_t launch_sg_finish(float* grad, int64_t n, const float* raw, float w_conf, float* stats, hipStream_t stream) {
+  if (!(w_conf >= 0.f)) hc::violation("k_sg_finish: confidence weight %g", w_conf);
   hc::need(grad, static_cast<size_t>(n) * 4, "k_sg_finish gradient");
   hc::need(raw, 6 * 4, "k_sg_finish sums");
   hc::need(stats, kSgTrainStats * 4, "k_sg_finish stats");
@@ -382,14 +383,18 @@ hipError_t launch_sg_adam(float* params, const float* grad, float* m, float* v, 
 }
 
 hipError_t launch_sg_merge(const SgMergeParams& p, hipStream_t stream) {
-  const size_t n = static_cast<size_t>(p.n);
+  const size_t n = static_cast<size_t>(p.n), sn = static_cast<size_t>(p.src_n);
+  if (p.begin < 0 || p.count < 1 || p.begin + p.count > p.n || p.begin - p.src_shift < 0 ||
+      p.begin + p.count - p.src_shift > p.src_n)
+    hc::violation("k_sg_merge: run [%lld, +%lld) of %lld, source shift %lld of %lld", (long long)p.begin,
+                  (long long)p.count, (long long)p.n, (long long)p.src_shift, (long long)p.src_n);
   hc::need(p.conf, n * 4, "k_sg_merge confidence");
   if (p.mask) hc::need(p.mask, n, "k_sg_merge mask");
-  if (p.e3) { hc::need(p.e3, 3 * n * 4, "k_sg_merge e3"); hc::need(p.pe3, 3 * n * 4, "k_sg_merge plain e3"); }
-  if (p.fa) { hc::need(p.fa, n * 4, "k_sg_merge fa"); hc::need(p.pfa, n * 4, "k_sg_merge plain fa"); }
-  if (p.ha) { hc::need(p.ha, n * 4, "k_sg_merge ha"); hc::need(p.pha, n * 4, "k_sg_merge plain ha"); }
-  if (p.ia) { hc::need(p.ia, n * 4, "k_sg_merge ia"); hc::need(p.pia, n * 4, "k_sg_merge plain ia"); }
-  grid_ok(cdiv(p.n, 256), "k_sg_merge");
+  if (p.e3) { hc::need(p.e3, 3 * n * 4, "k_sg_merge e3"); hc::need(p.pe3, 3 * sn * 4, "k_sg_merge plain e3"); }
+  if (p.fa) { hc::need(p.fa, n * 4, "k_sg_merge fa"); hc::need(p.pfa, sn * 4, "k_sg_merge plain fa"); }
+  if (p.ha) { hc::need(p.ha, n * 4, "k_sg_merge ha"); hc::need(p.pha, sn * 4, "k_sg_merge plain ha"); }
+  if (p.ia) { hc::need(p.ia, n * 4, "k_sg_merge ia"); hc::need(p.pia, sn * 4, "k_sg_merge plain ia"); }
+  grid_ok(cdiv(p.count, 256), "k_sg_merge");
   hc::kernel_launch(stream, "k_sg_merge");
   return hipSuccess;
 }

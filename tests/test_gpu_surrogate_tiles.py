@@ -101,3 +101,17 @@ def test_every_voxel_takes_the_whole_volume_path(scene):
     nlow, nin = _expect(pure, mixed, plain, None, 1.0)
     _log(f"  {info}, {nlow} of {nin} voxels fell back")
     assert info["mode"] == 2 and info["voxels"] == vol.numel(), info
+
+
+def test_streamed_whole_volume_fallback_matches(scene, monkeypatch):
+    """A whole-volume fallback streamed in z slabs through small activation
+    buffers (forced with ST_SURROGATE_SLAB_BYTES: 24-plane buffers, about 40
+    planes of the path per slab, 16 of them its own at sigma 1, rho 2) gives
+    st_compute's outputs bit for bit."""
+    vol, _, blob, center, direction = scene
+    monkeypatch.setenv("ST_SURROGATE_SLAB_BYTES", str(2 * 24 * SHAPE[1] * SHAPE[2] * 64))
+    _log("case: streamed whole-volume fallback, sigma 1, rho 2")
+    pure, mixed, plain, info = _run(vol, None, blob, center, direction, 1.0, 2.0, 1.0)
+    nlow, nin = _expect(pure, mixed, plain, None, 1.0)
+    _log(f"  {info}, {nlow} of {nin} voxels fell back")
+    assert info["mode"] == 2 and nlow > nin // 2, info

@@ -65,17 +65,17 @@ def _case(seed, npatch, P, dtype):
     return blob.astype(np.float32), vol, t.astype(np.float32), fa.astype(np.float32), w
 
 
-def _oracle(blob, vol, t, fa, w, npatch, P):
+def _oracle(blob, vol, t, fa, w, npatch, P, conf_weight=0.1):
     pt = vol.astype(np.float64).reshape(npatch, P, P, P)
     tt = t.astype(np.float64).reshape(3, npatch, P, P, P).transpose(1, 0, 2, 3, 4)
     return S.train_loss_grad(blob.astype(np.float64), pt, tt, fa.astype(np.float64).reshape(npatch, P, P, P),
-                             w.astype(np.float64).reshape(npatch, P, P, P))
+                             w.astype(np.float64).reshape(npatch, P, P, P), conf_weight=conf_weight)
 
 
-def _gpu(blob, vol, t, fa, w):
+def _gpu(blob, vol, t, fa, w, conf_weight=0.1):
     g, s = st.st_surrogate_grad(torch.from_numpy(vol).to(DEV), torch.from_numpy(t).to(DEV),
                                 torch.from_numpy(fa).to(DEV), torch.from_numpy(w).to(DEV),
-                                torch.from_numpy(blob).to(DEV))
+                                torch.from_numpy(blob).to(DEV), conf_weight=conf_weight)
     torch.cuda.synchronize()
     return g.cpu().numpy().astype(np.float64), s.cpu().numpy().astype(np.float64)
 
@@ -104,6 +104,7 @@ def _compare(g, s, o):
         got[name] = float(np.linalg.norm(g[sl] - ref) / max(np.linalg.norm(ref), 1e-30))
     _log({k: f"{v:.2e}" for k, v in got.items()})
     assert got["wsum"] == 0, got
+    assert abs(s[3] - o["loss"]) <= LOSS_TOL * abs(o["loss"]), (s[3], o["loss"])
     assert g[0] == 0 and g[1] == 0  # in_scale and in_offset are not trained
     assert max(got["loss_dir"], got["loss_fa"], got["loss_conf"]) <= LOSS_TOL, got
     assert got["within"] <= max(2, 1e-3 * o["wsum"]), got
@@ -111,12 +112,13 @@ def _compare(g, s, o):
     assert max(groups.values()) <= GROUP_TOL, groups
 
 
-@pytest.mark.parametrize("seed,npatch,P,dtype", [(1, 2, 16, "u16"), (2, 1, 24, "f32"), (3, 3, 12, "u16")])
-def test_gradient_matches_oracle(seed, npatch, P, dtype):
-    _log("case: surrogate gradient", npatch, "patches of", P, dtype)
+@pytest.mark.parametrize("seed,npatch,P,dtype,cw", [(1, 2, 16, "u16", 0.1), (2, 1, 24, "f32", 0.1),
+                                                    (3, 3, 12, "u16", 0.1), (4, 2, 16, "u16", 1.0)])
+def test_gradient_matches_oracle(seed, npatch, P, dtype, cw):
+    _log("case: surrogate gradient", npatch, "patches of", P, dtype, "confidence weight", cw)
     blob, vol, t, fa, w = _case(seed, npatch, P, dtype)
-    g, s = _gpu(blob, vol, t, fa, w)
-    _compare(g, s, _oracle(blob, vol, t, fa, w, npatch, P))
+    g, s = _gpu(blob, vol, t, fa, w, cw)
+    _compare(g, s, _oracle(blob, vol, t, fa, w, npatch, P, cw))
 
 
 def test_training_size_patch():

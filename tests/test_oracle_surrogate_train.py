@@ -113,3 +113,20 @@ def test_constant_network_closed_form():
     # x5 = relu(b5) = 0, so the head weights and every earlier layer get nothing;
     # the FA entry is zero up to the rounding of sigmoid(logit(0.3))
     assert np.abs(g[:n - 1]).max() <= 1e-15
+    # the confidence term's weight scales its gradient and its share of L only
+    o3 = S.train_loss_grad(blob, pt, t, fa, wt, round_bf16=False, conf_weight=0.7)
+    assert o3["grad"][n - 1] == pytest.approx(0.7 * (1 / (1 + np.exp(-1.5)) - 1.0), rel=1e-12)
+    assert o3["loss"] == pytest.approx(0.7 * np.log1p(np.exp(-1.5)), rel=1e-12)
+    assert o3["loss_conf"] == o["loss_conf"]
+
+
+def test_confidence_weight_splits_the_gradient_linearly():
+    # the gradient is linear in the confidence term's weight: the part of every
+    # parameter's gradient that comes from l_conf scales with it, the rest stays
+    rng = np.random.default_rng(9)
+    blob = _blob(rng)
+    pt, t, fa, wt = _batch(rng, B=1, P=12)
+    g = {cw: S.train_loss_grad(blob, pt, t, fa, wt, round_bf16=False, conf_weight=cw)["grad"]
+         for cw in (0.0, 0.1, 1.0)}
+    np.testing.assert_allclose(g[1.0] - g[0.0], 10.0 * (g[0.1] - g[0.0]), rtol=1e-9, atol=1e-14)
+    assert np.abs(g[1.0] - g[0.0]).max() > 0
