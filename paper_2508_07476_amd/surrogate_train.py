@@ -26,7 +26,7 @@ in a fresh order every epoch.  Held-out phantoms, drawn from other seeds, give
 the reported angle error of st_surrogate_infer against st_compute and the
 fallback fraction at the confidence threshold.
 
-Usage (on a GPU machine):
+Usage (on a GPU machine; the defaults reproduce the shipped weights):
   python -m paper_2508_07476_amd.surrogate_train out.npy [--patches 100000] [--epochs E]
 """
 
@@ -192,14 +192,14 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("--patches", type=int, default=100_000)
-    ap.add_argument("--epochs", type=float, default=4.0)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--epochs", type=float, default=16.0)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--patch", type=int, default=32)
-    ap.add_argument("--volumes", type=int, default=48)
+    ap.add_argument("--volumes", type=int, default=128)
     ap.add_argument("--shape", type=int, default=128)
     ap.add_argument("--sigma", type=float, default=1.0)
     ap.add_argument("--rho", type=float, default=2.0)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--conf-weight", type=float, default=0.1, help="weight of the confidence term")
     ap.add_argument("--min-weight", type=int, default=2000)
