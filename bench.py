@@ -461,8 +461,9 @@ BATCH_OUTPUTS = ("e3", "fa", "ha", "ia", "flags")
 def run_batch(args, torch, st, helix, dev):
     """Chunk-batch workload (200 halo-padded chunks): the autotuned batch is the
     line's value; beside it the untuned 8-chain graph, the untuned grouped
-    launches and one st_compute per chunk on one stream.  Inputs resident; the
-    four share one set of output tensors."""
+    launches (in the batch's own 8-slot workspace, and in one holding every
+    chunk: a single round) and one st_compute per chunk on one stream.  Inputs
+    resident; all share one set of output tensors."""
     spec = helix.spec_headline_u16(shape=SHAPE)
     ph = helix.generate(spec, device=dev)
     crops = helix.batch_crops(SHAPE)
@@ -498,6 +499,20 @@ def run_batch(args, torch, st, helix, dev):
                        "config": b.config(), "plan": b.plan()}
         b.close()
         torch.cuda.empty_cache()
+    # grouped launches with a workspace holding every chunk: one round, one
+    # launch per pass kind (when the device has room for it)
+    one = sum((st.st_workspace_bytes(tuple(c["volume"].shape)) + 255) // 256 * 256 for c in chunks)
+    if torch.cuda.mem_get_info(dev)[0] > one + (8 << 30):
+        ws1 = torch.empty(one, dtype=torch.uint8, device=dev)
+        b = st.Batch(chunks, BATCH_SIGMA, TRUNCATE, lanes=st.ST_BATCH_GROUPED, results=results, workspace=ws1, **kw)
+        ms = timed(b.launch, args.steps)
+        modes["grouped_one_round"] = {"ms_per_step": round(ms, 4), "value": round(nvox / ms / 1e6, 4),
+                                      "unit": "Gvoxels/s", "workspace_bytes": one, "plan": b.plan()}
+        b.close()
+        del ws1
+        torch.cuda.empty_cache()
+    else:
+        modes["grouped_one_round"] = {"skipped": f"needs {one} workspace bytes"}
     b = st.Batch(chunks, BATCH_SIGMA, TRUNCATE, lanes=0, results=results, **kw)
     t0 = time.perf_counter()
     cfg = b.tune(reps=2)
@@ -551,6 +566,9 @@ def main():
                     help="skip the learned surrogate's 1024^3 leg of the default run")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 512^3 figure that follows the default workload")
+    ap.add_argument("--path-only", nargs=4, metavar=("SHAPE", "SIGMA", "RHO", "CALLS"), default=None,
+                    help="only call st_compute CALLS times on the 512^3-geometry phantom of SHAPE (e.g. "
+                         "512x512x512) at SIGMA, RHO (for counter collection)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write elementwise kernel (for scaling HBM "
                          "byte counters)")
@@ -588,6 +606,19 @@ def main():
         return
     torch.cuda.set_device(dev)
     st.load_library()
+    if args.path_only:
+        shape = tuple(int(v) for v in args.path_only[0].split("x"))
+        sigma, rho, calls = float(args.path_only[1]), float(args.path_only[2]), int(args.path_only[3])
+        ph = helix.generate(helix.spec_headline_u16(shape=shape), device=dev)
+        outs = ("e3", "fa", "ha", "ia")
+        out = {k: torch.empty(((3,) if k == "e3" else ()) + shape, dtype=torch.float32, device=dev) for k in outs}
+        ws = torch.empty(st.st_workspace_bytes(shape), dtype=torch.uint8, device=dev)
+        for _ in range(calls):
+            st.st_compute(ph["volume"], sigma, rho, TRUNCATE, mask=ph["mask"], axis_center=ph["center"],
+                          axis_direction=ph["direction"], outputs=outs, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"path_only": {"shape": shape, "sigma": sigma, "rho": rho, "calls": calls}}))
+        return
     if args.batch:
         return run_batch(args, torch, st, helix, dev)
     if args.surrogate:
