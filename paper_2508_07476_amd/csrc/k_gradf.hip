@@ -12,9 +12,12 @@
 // each side, reflected at the faces) the (TY + 2R) x (64 + 2R) input tile is
 // staged in LDS; the next
 // plane's loads are issued before the current plane is filtered.  Each
-// column's z window lives in registers and shifts by one plane per step.
+// column's z window lives in registers; the plane loop is expanded to the window
+// length (a fold over an index sequence), so every plane's results land in a
+// register fixed at compile time and the window never moves.
 // Products leave with non-temporal stores into workspace planes whose rows have
 // the workspace pitch (the input volume has rows of nx).
+#include <utility>
 #include "st_device.h"
 
 namespace st {
@@ -121,41 +124,44 @@ __device__ __forceinline__ void grad_fused_block(const GradGeo& p, const Taps& w
   const int64_t out_col = (y0 + ty) * p.opitch + (x0 + tx);
   const int64_t out_plane = ny * p.opitch;
 
-  // z windows: w*[k] holds the column's partial results of input plane
-  // (current output z) - R + k; they shift by one plane per step (a rolled loop
-  // keeps the code and the register count small).
+  // z windows: slot (j + k) mod W of w* holds the column's partial results of
+  // input plane j - 2R + k at plane step j; the plane loop is expanded W times
+  // so that every slot index is static (no register moves)
   double wa[W], wb[W], wc[W];
   fetch(z0 - R);
   const int nplanes = len + 2 * R;
 #pragma unroll 1
-  for (int j = 0; j < nplanes; ++j) {  // block-uniform trip count
-    double a, bq, c;
-    filter_plane(z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
+  for (int jb = 0; jb < nplanes; jb += W) {  // block-uniform trip count
+    auto step = [&]<int J>(std::integral_constant<int, J>) {
+      const int j = jb + J;
+      if (j < nplanes) {
+        double a, bq, c;
+        filter_plane(z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
+        constexpr int S = (J + 2 * R) % W;
+        wa[S] = a;
+        wb[S] = bq;
+        wc[S] = c;
+        if (j >= 2 * R && active) {
+          double gz = 0.0, gy = 0.0, gx = 0.0;
 #pragma unroll
-    for (int k = 0; k < W - 1; ++k) {
-      wa[k] = wa[k + 1];
-      wb[k] = wb[k + 1];
-      wc[k] = wc[k + 1];
-    }
-    wa[W - 1] = a;
-    wb[W - 1] = bq;
-    wc[W - 1] = c;
-    if (j >= 2 * R && active) {
-      double gz = 0.0, gy = 0.0, gx = 0.0;
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        gz = fma(wd.w[k], wa[k], gz);
-        gy = fma(tg(k), wb[k], gy);
-        gx = fma(tg(k), wc[k], gx);
+          for (int k = 0; k < W; ++k) {
+            gz = fma(wd.w[k], wa[(J + k) % W], gz);
+            gy = fma(tg(k), wb[(J + k) % W], gy);
+            gx = fma(tg(k), wc[(J + k) % W], gx);
+          }
+          const int64_t i = static_cast<int64_t>(z0 + j - 2 * R) * out_plane + out_col;
+          __builtin_nontemporal_store(static_cast<float>(gz * gz), p.prod[0] + i);
+          __builtin_nontemporal_store(static_cast<float>(gz * gy), p.prod[1] + i);
+          __builtin_nontemporal_store(static_cast<float>(gz * gx), p.prod[2] + i);
+          __builtin_nontemporal_store(static_cast<float>(gy * gy), p.prod[3] + i);
+          __builtin_nontemporal_store(static_cast<float>(gy * gx), p.prod[4] + i);
+          __builtin_nontemporal_store(static_cast<float>(gx * gx), p.prod[5] + i);
+        }
       }
-      const int64_t i = static_cast<int64_t>(z0 + j - 2 * R) * out_plane + out_col;
-      __builtin_nontemporal_store(static_cast<float>(gz * gz), p.prod[0] + i);
-      __builtin_nontemporal_store(static_cast<float>(gz * gy), p.prod[1] + i);
-      __builtin_nontemporal_store(static_cast<float>(gz * gx), p.prod[2] + i);
-      __builtin_nontemporal_store(static_cast<float>(gy * gy), p.prod[3] + i);
-      __builtin_nontemporal_store(static_cast<float>(gy * gx), p.prod[4] + i);
-      __builtin_nontemporal_store(static_cast<float>(gx * gx), p.prod[5] + i);
-    }
+    };
+    [&]<int... J>(std::integer_sequence<int, J...>) {
+      (step(std::integral_constant<int, J>{}), ...);
+    }(std::make_integer_sequence<int, W>{});
   }
 }
 
