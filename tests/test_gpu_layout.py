@@ -5,7 +5,9 @@ and the final pass covers a row with 256-output segments or, for narrow rows
 and radii up to 16, with 64-output segments of four consecutive rows.  These
 cases sit on both sides of each boundary, with a row count (nz * ny = 35) that
 is not a multiple of four, so the last wave of 64-output segments holds rows
-past the end; the radius-20 case must take 256-output segments.
+past the end; the radius-20 cases must take 256-output segments (one row
+narrower than a segment, the others on both sides of two segments' width,
+with rows that start off 16 bytes).
 """
 
 import sys
@@ -26,7 +28,8 @@ ALL = ("e3", "evals", "fa", "ha", "ia", "flags")
 
 
 @pytest.mark.parametrize("nx,rho", [(31, 2.0), (32, 2.0), (33, 2.0), (63, 2.0), (64, 3.0), (65, 3.0),
-                                    (255, 2.0), (256, 4.0), (257, 2.0), (97, 5.0)])
+                                    (255, 2.0), (256, 4.0), (257, 2.0), (97, 5.0),
+                                    (511, 5.0), (512, 5.0), (513, 5.0)])
 def test_widths_at_layout_boundaries(nx, rho):
     shape = (5, 7, nx)
     print(f"case: shape={shape} rho={rho}", file=sys.stderr, flush=True)
