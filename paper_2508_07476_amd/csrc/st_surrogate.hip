@@ -321,7 +321,8 @@ int tile_fallback(const FallbackPlan& plan, const void* volume, int dtype, const
     const int d = st_batch_destroy(batch);
     if (status == ST_OK && e == hipSuccess && d != ST_OK) status = d;
   }
-  if (e != hipSuccess) (void)hipStreamSynchronize(stream);
+  // on an error, work already enqueued may still read or write the crops
+  if (status != ST_OK || e != hipSuccess) (void)hipStreamSynchronize(stream);
   const hipError_t f = hipFree(ws);
   if (status != ST_OK) return status;
   if (e != hipSuccess) return device_fail(e, stage);
