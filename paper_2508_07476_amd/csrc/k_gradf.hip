@@ -10,8 +10,13 @@
 // four waves per SIMD without spilling, else 4; a 4-row variant is also built
 // up to radius 6 for the batch autotuner).  For every input plane (z halo of R on
 // each side, reflected at the faces) the (TY + 2R) x (64 + 2R) input tile is
-// staged in LDS; the next
-// plane's loads are issued before the current plane is filtered.  Each
+// staged in LDS, in two buffers used by alternate planes; the next plane's
+// loads are issued before the current plane is filtered.  Each wave filters
+// along y the 64 + 2R columns of its own tile row, which only it reads in the
+// x filter, so one block barrier per plane (after the staging) suffices: a
+// wave that writes plane j + 1's buffer has passed plane j's barrier, and one
+// that would overwrite plane j's buffer (at j + 2) waits at plane j + 1's for
+// every wave to finish reading it.  Each
 // column's z window lives in registers; the plane loop is expanded to the window
 // length (a fold over an index sequence), so every plane's results land in a
 // register fixed at compile time and the window never moves.
@@ -31,11 +36,10 @@ __device__ __forceinline__ void grad_fused_block(const GradGeo& p, const Taps& w
   constexpr int NT = TX * TY;  // threads: one per output column of the tile
   constexpr int RX = TX + 2 * R, RY = TY + 2 * R;
   constexpr int NSTAGE = (RX * RY + NT - 1) / NT;  // staged elements per thread
-  constexpr int NYPOS = (TY * RX + NT - 1) / NT;   // y-filter positions per thread
   // The smoothing taps are symmetric about the centre (bit for bit, as built):
   // only taps 0..R are read, so R + 1 of them occupy scalar registers.
   auto tg = [&](int k) { return wg.w[k <= R ? k : 2 * R - k]; };
-  __shared__ float raw[RY * RX];      // input plane (exact in float32)
+  __shared__ float raw[2][RY * RX];   // input planes (exact in float32), alternating
   __shared__ double yb[2][TY * RX];   // y-filtered plane, float64
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
@@ -76,33 +80,38 @@ __device__ __forceinline__ void grad_fused_block(const GradGeo& p, const Taps& w
     for (int j = 0; j < NSTAGE; ++j) pf[j] = static_cast<float>(src[off[j]]);  // halo re-read by neighbours: keep cached
   };
 
-  // Filter the staged plane (already fetched into pf) along y then x; returns the
-  // three partial results of this thread's column, and prefetches plane `next`.
-  auto filter_plane = [&](int next, bool has_next, double& a, double& bq, double& c) {
+  // Stage plane step j (already fetched into pf) and filter it along y then x;
+  // returns the three partial results of this thread's column, and prefetches
+  // plane `next`.
+  auto filter_plane = [&](int j, int next, bool has_next, double& a, double& bq, double& c) {
+    float* rb = raw[j & 1];
 #pragma unroll
-    for (int j = 0; j < NSTAGE; ++j) {
-      const int s = tid + NT * j;
-      if (s < RX * RY) raw[s] = pf[j];
+    for (int t = 0; t < NSTAGE; ++t) {
+      const int s = tid + NT * t;
+      if (s < RX * RY) rb[s] = pf[t];
     }
     if (has_next) fetch(next);
     __syncthreads();
+    // y filter of the wave's own row (columns tx and tx + 64 of RX): only this
+    // wave reads it, so no block barrier separates it from the x filter
 #pragma unroll
-    for (int q = 0; q < NYPOS; ++q) {
-      const int s = tid + NT * q;
-      if (s < TY * RX) {
-        const int row = s / RX, col = s - (s / RX) * RX;
+    for (int q = 0; q < (RX + 63) / 64; ++q) {
+      const int col = tx + 64 * q;
+      if (col < RX) {
         double g = 0.0, d = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const double v = raw[(row + k) * RX + col];
+          const double v = rb[(ty + k) * RX + col];
           g = fma(tg(k), v, g);
           d = fma(wd.w[k], v, d);
         }
-        yb[0][s] = g;
-        yb[1][s] = d;
+        yb[0][ty * RX + col] = g;
+        yb[1][ty * RX + col] = d;
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double ga = 0.0, gb = 0.0, dc = 0.0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
@@ -136,7 +145,7 @@ __device__ __forceinline__ void grad_fused_block(const GradGeo& p, const Taps& w
       const int j = jb + J;
       if (j < nplanes) {
         double a, bq, c;
-        filter_plane(z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
+        filter_plane(j, z0 - R + j + 1, j + 1 < nplanes, a, bq, c);
         constexpr int S = (J + 2 * R) % W;
         wa[S] = a;
         wb[S] = bq;
