@@ -6,10 +6,13 @@
 // consecutive rows.  It stages each segment plus a halo of R samples on each
 // side in LDS (coalesced global loads, boundary reflection per lane only for
 // segments that touch a face), then every lane computes kXVec = 4 consecutive
-// outputs, streaming its 2R+4 window from LDS in 16-byte pieces: each value is
-// widened to float64 once and feeds up to 4 outputs.  Intermediate planes are
-// read and written with the workspace row pitch; the caller's mask and outputs
-// with rows of nx.
+// outputs, streaming its 2R+4 window from LDS in 16-byte pieces: each value
+// feeds up to 4 outputs.  Values are widened to float64 as the window streams
+// by, or, in the final pass's 64-lane segments, once as they are staged (the
+// rows of three components at a time, in the bytes of six float32 rows), since
+// a staged value lies in the windows of up to R / 2 + 1 lanes.  Intermediate
+// planes are read and written with the workspace row pitch; the caller's mask
+// and outputs with rows of nx.
 #pragma once
 #include "st_device.h"
 
@@ -81,6 +84,31 @@ __device__ __forceinline__ void conv4(const float* lds, int lane, const Taps& w,
         const int k = j - v;
         const int kk = SYMMETRIC && k > R ? 2 * R - k : k;
         if (k >= 0 && k <= 2 * R) out[v] = fma(w.w[kk], d, out[v]);
+      }
+    }
+  }
+}
+
+// conv4 over a window already widened to float64 in LDS (16-byte reads of two
+// values); the same sums in the same order as conv4 on the float32 row.
+template <int R, bool SYMMETRIC = false>
+__device__ __forceinline__ void conv4_f64(const double* lds, int lane, const Taps& w, double out[kXVec]) {
+  constexpr int NP = (2 * R + kXVec + 1) / 2;
+  const double2* src = reinterpret_cast<const double2*>(lds + 4 * lane);
+#pragma unroll
+  for (int v = 0; v < kXVec; ++v) out[v] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const double2 t = src[q];
+    const double e[2] = {t.x, t.y};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = 2 * q + u;
+#pragma unroll
+      for (int v = 0; v < kXVec; ++v) {
+        const int k = j - v;
+        const int kk = SYMMETRIC && k > R ? 2 * R - k : k;
+        if (k >= 0 && k <= 2 * R) out[v] = fma(w.w[kk], e[u], out[v]);
       }
     }
   }
@@ -168,14 +196,7 @@ __device__ __forceinline__ void xfinal_block(const XFinalGeo& p, const Taps& w, 
 #pragma unroll
   for (int c = 0; c < 6; ++c) seg[c] = &lds[c][sub * LR];
 
-  {
-    int idx[stage_slots(R, TL)];
-    stage_index<R, TL>(idx, x0, p.nx, l);
-    const int64_t sbase = rr * p.pitch;  // integrated products: workspace rows
-#pragma unroll
-    for (int c = 0; c < 6; ++c) stage_row<R, TL>(seg[c], p.s[c] + sbase, idx, l);
-  }
-  // mask bytes of the lane's voxels, fetched now so the loads overlap the filtering
+  // mask bytes of the lane's voxels, fetched first so the loads overlap the filtering
   uint32_t inside_bits = 0xFu;
   if (p.mask != nullptr) {
     inside_bits = 0u;
@@ -185,11 +206,42 @@ __device__ __forceinline__ void xfinal_block(const XFinalGeo& p, const Taps& w, 
       inside_bits |= (p.mask[base + xr] != 0 ? 1u : 0u) << v;
     }
   }
-  __syncthreads();
-
   double acc[6][kXVec];
+  if constexpr (TL == 64) {
+    // The six float32 rows' bytes hold three float64 rows: stage and integrate
+    // the components in two halves of three, widening every staged value once
+    // (a window value is read by up to four lanes' windows).
+    constexpr int NS = stage_slots(R, TL);
+    double* drow = reinterpret_cast<double*>(&lds[0][0]);
+    int idx[NS];
+    stage_index<R, TL>(idx, x0, p.nx, l);
+    const int64_t sbase = rr * p.pitch;  // integrated products: workspace rows
 #pragma unroll
-  for (int c = 0; c < 6; ++c) conv4<R, true>(seg[c], l, w, acc[c]);
+    for (int h = 0; h < 2; ++h) {
+      float v[3][NS];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) v[c][j] = p.s[3 * h + c][sbase + idx[j]];
+      if (h == 1) __syncthreads();  // the first half's windows are read
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) drow[c * LR + l + TL * j] = static_cast<double>(v[c][j]);
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 3; ++c) conv4_f64<R, true>(drow + c * LR, l, w, acc[3 * h + c]);
+    }
+  } else {
+    int idx[stage_slots(R, TL)];
+    stage_index<R, TL>(idx, x0, p.nx, l);
+    const int64_t sbase = rr * p.pitch;  // integrated products: workspace rows
+#pragma unroll
+    for (int c = 0; c < 6; ++c) stage_row<R, TL>(seg[c], p.s[c] + sbase, idx, l);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 6; ++c) conv4<R, true>(seg[c], l, w, acc[c]);
+  }
   __syncthreads();  // every window read before the rows receive results
 
   // (z, y) of the lane's row; with several rows per wave the wave's first row
