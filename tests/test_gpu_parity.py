@@ -163,6 +163,25 @@ def test_deterministic_bitwise():
         assert torch.equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("sigma,rho", [(2.0, 6.0), (1.5, 4.0)])
+def test_deterministic_bitwise_fused_gradient_and_final_pass(sigma, rho):
+    """Race smoke test of the LDS-staged passes at the radii whose tiles keep
+    several blocks per CU: the fused gradient's one barrier per plane over two
+    alternating plane buffers (radius 8 with 4-row tiles, radius 6 with 8-row
+    tiles) and the final pass's float64 rows staged in two halves (radius 24,
+    16).  Three runs on a 96 x 192 x 520 volume (rows past one 256-output
+    segment, a ragged last tile) must agree bit for bit."""
+    _log(f"case: determinism sigma={sigma} rho={rho}")
+    ph = helix.generate(helix.PhantomSpec(shape=(96, 192, 520), annuli=(helix.Annulus(30.0, 90.0),), period=4.0,
+                                          noise=(0.05,), dtype="u16", seed=9, with_mask=True), device=DEV)
+    kw = dict(mask=ph["mask"], axis_center=ph["center"], axis_direction=ph["direction"], outputs=ALL)
+    runs = [st.st_compute(ph["volume"], sigma, rho, **kw) for _ in range(3)]
+    torch.cuda.synchronize()
+    for r in runs[1:]:
+        for k in ALL:
+            assert torch.equal(runs[0][k], r[k]), k
+
+
 def test_standalone_angles_match_oracle_frame():
     spec = helix.spec_small_f32()
     ph = helix.generate(spec)
