@@ -210,7 +210,7 @@ __device__ __forceinline__ void xfinal_block(const XFinalGeo& p, const Taps& w, 
   if constexpr (TL == 64) {
     // The six float32 rows' bytes hold three float64 rows: stage and integrate
     // the components in two halves of three, widening every staged value once
-    // (a window value is read by up to four lanes' windows).
+    // (it lies in the windows of up to R / 2 + 1 lanes).
     constexpr int NS = stage_slots(R, TL);
     double* drow = reinterpret_cast<double*>(&lds[0][0]);
     int idx[NS];
