@@ -271,8 +271,9 @@ __global__ __launch_bounds__(NT) void k_sg_conv(const SgConvParams p) {
 // of 3 LDS planes of 10 x 66 voxels (faces clamped; 124 KB, one block per CU);
 // the next plane's loads are issued before the current plane's products and
 // stored into the ring right after them, before the epilogue.
-// LAST: the head is reduced across the four lanes that share a voxel (each
-// holds 8 of its 32 channels), so no LDS is needed for it.
+// LAST: the head is three more MFMAs per N block: the layer's output and the
+// head weights each split into a high and a low bf16 part (about 16 bits of
+// each), all products but low x low.
 constexpr int WS_TY = 8, WS_TX = 64, WS_RY = WS_TY + 2, WS_RX = WS_TX + 2;
 constexpr int WS_NT = 256;
 constexpr int WS_PLANE = WS_RY * WS_RX;
@@ -342,6 +343,21 @@ __global__ __launch_bounds__(WS_NT) void k_sg_conv_ws(const SgConvParams p) {
   store_plane(2, pf);
   __syncthreads();
 
+  // LAST: the head h = Wh x5 on the matrix cores, with Wh (rows 0..4 of a
+  // 16-row A operand) split into a bf16 high and low part.  A lane's B operand
+  // is its own eight channels of x5, so its K index 8 lk + i stands for
+  // channel 16 (i / 4) + 4 lk + i % 4, and A's columns follow that order.
+  bf16x8 wh_hi, wh_lo;
+  if constexpr (LAST) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float wv = li < 5 ? hw[li * C + 16 * (i >> 2) + 4 * lk + (i & 3)] : 0.f;
+      const __bf16 hi = static_cast<__bf16>(wv);
+      wh_hi[i] = hi;
+      wh_lo[i] = static_cast<__bf16>(wv - static_cast<float>(hi));
+    }
+  }
+
   const bf16x8* a8 = reinterpret_cast<const bf16x8*>(al);
 #pragma unroll 1
   for (int64_t z = z0; z < z1; ++z) {
@@ -393,28 +409,32 @@ __global__ __launch_bounds__(WS_NT) void k_sg_conv_ws(const SgConvParams p) {
         }
       }
     } else {
-      // head: each lane sums its 8 channels, the 4 lanes of a voxel (lk = 0..3)
-      // add theirs; lanes of group lk then finish the voxels of N blocks lk, lk + 4
+      // head: x5 = relu(acc + b), split like Wh into a high and a low bf16
+      // part, is the B operand as the lane holds it (the product of the two
+      // low parts, below 2^-16 of a term, is left out); D row q, column li is
+      // h[q] of voxel li (rows 0..3 in lanes 0..15, row 4 in lanes 16..31).
+      // Lanes of group lk then finish the voxels of N blocks lk and lk + 4.
       float hs[2][5];
 #pragma unroll
       for (int n = 0; n < 8; ++n) {
-        float part[5];
+        bf16x8 xh, xl;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) part[q] = 0.f;
+        for (int i = 0; i < 8; ++i) {
+          const float v = fmaxf(acc[i >> 2][n][i & 3] + bias[i >> 2][i & 3], 0.f);
+          xh[i] = static_cast<__bf16>(v);
+          xl[i] = static_cast<__bf16>(v - static_cast<float>(xh[i]));
+        }
+        f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh_hi, xh, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh_hi, xl, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh_lo, xh, d, 0, 0, 0);
+        float qv[5];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int r = 0; r < 4; ++r) qv[r] = __shfl(d[r], li);
+        qv[4] = __shfl(d[0], 16 + li);
+        if ((n & 3) == lk) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float v = fmaxf(acc[m][n][r] + bias[m][r], 0.f);
-            const int co = 16 * m + 4 * lk + r;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) part[q] = fmaf(hw[q * C + co], v, part[q]);
-          }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          part[q] += __shfl_xor(part[q], 16);
-          part[q] += __shfl_xor(part[q], 32);
-          if ((n & 3) == lk) hs[n >> 2][q] = part[q];
+          for (int q = 0; q < 5; ++q) hs[n >> 2][q] = qv[q];
         }
       }
 #pragma unroll
