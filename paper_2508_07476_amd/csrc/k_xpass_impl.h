@@ -257,6 +257,7 @@ __device__ __forceinline__ void xfinal_block(const XFinalGeo& p, const Taps& w, 
     py = static_cast<double>(pyi);
   }
   const int64_t n = p.n;
+  uint32_t flag_word = 0u;  // the lane's flag bytes, voxel v in byte v
 #pragma unroll 1
   for (int v = 0; v < kXVec; ++v) {
     const int xv = x + v;
@@ -287,10 +288,21 @@ __device__ __forceinline__ void xfinal_block(const XFinalGeo& p, const Taps& w, 
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) seg[q][kXVec * l + v] = res[q];
-    if (row_ok && xv < nxi) {  // optional outputs: scalar stores
+    if (row_ok && xv < nxi && p.evals) {  // optional output: scalar stores
       const int64_t i = base + xv;
-      if (p.evals) { p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3; }
-      if (p.flags) p.flags[i] = static_cast<uint8_t>(fl);
+      p.evals[i] = l1; p.evals[n + i] = l2; p.evals[2 * n + i] = l3;
+    }
+    flag_word |= (fl & 0xffu) << (8 * v);
+  }
+  if (p.flags != nullptr && row_ok && x < nxi) {
+    // the lane's four flag bytes as one aligned 32-bit store where they are
+    // whole (x is a multiple of 4), else one byte at a time
+    if (p.vec_ok != 0 && ((base + x) & 3) == 0 && x + kXVec <= nxi) {
+      *reinterpret_cast<uint32_t*>(p.flags + base + x) = flag_word;
+    } else {
+#pragma unroll
+      for (int v = 0; v < kXVec; ++v)
+        if (x + v < nxi) p.flags[base + x + v] = static_cast<uint8_t>(flag_word >> (8 * v));
     }
   }
   if constexpr (TL == 64) {
