@@ -71,6 +71,8 @@ CASES = [
     ((130, 12, 9), "f32", 1.2, 6.0, False, (1.0, 0.5, 0.0)),   # long z axis (several chunks), R 24
     ((26, 44, 90), "u16", 2.6, 3.0, True, (1.0, -0.4, 0.3)),   # sigma radius 10: three-pass gradient
     ((70, 9, 131), "f32", 2.0, 2.0, False, (0.0, 1.0, 1.0)),   # sigma radius 8: largest fused gradient
+    ((40, 36, 200), "f32", 3.6, 7.9, True, (1.0, 0.2, 0.1)),   # sigma radius 14, rho radius 32 (largest)
+    ((72, 30, 129), "u16", 4.0, 7.0, False, (0.0, 1.0, 0.0)),  # sigma radius 16 (largest), rho radius 28
 ]
 
 
