@@ -162,6 +162,40 @@ def test_grouped_batch_matches_chains_bitwise(phantom):
         del ws
 
 
+# small integration scales (rho radius 2 and 4) on narrow rows: the 16-lane
+# final-pass segments of those radii, in chains and in grouped launches
+CROPS_SMALL_RHO = [((10, 20, 30), (40, 52, 36), 0.5), ((0, 0, 0), (64, 40, 48), 1.0),
+                   ((30, 5, 8), (33, 47, 70), 1.0), ((20, 30, 2), (20, 25, 50), 0.5)]
+
+
+def test_small_rho_chunks_chains_grouped_and_single_calls_agree(phantom):
+    chunks = []
+    for i, (org, shp, rho) in enumerate(CROPS_SMALL_RHO):
+        c = {"volume": _crop(phantom["volume"], org, shp).to(DEV), "rho": rho, "origin": org}
+        if i % 2 == 1:
+            c["mask"] = _crop(phantom["mask"], org, shp).to(DEV)
+        chunks.append(c)
+    kw = dict(axis_center=phantom["center"], axis_direction=phantom["direction"], outputs=OUTS)
+    _log("case: small-rho chunks, chains / grouped / single calls")
+    chains = st.Batch(chunks, SIGMA, lanes=2, **kw)
+    chains.launch()
+    a = _snapshot(chains)
+    chains.close()
+    grouped = st.Batch(chunks, SIGMA, lanes=st.ST_BATCH_GROUPED, **kw)
+    assert grouped.plan()["grouped"]
+    grouped.launch()
+    b = _snapshot(grouped)
+    grouped.close()
+    for i, c in enumerate(chunks):
+        center = tuple(phantom["center"][d] - c["origin"][d] for d in range(3))
+        one = st.st_compute(c["volume"], SIGMA, c["rho"], mask=c.get("mask"), axis_center=center,
+                            axis_direction=phantom["direction"], outputs=OUTS)
+        torch.cuda.synchronize()
+        for k in OUTS:
+            assert torch.equal(a[i][k], one[k]), (i, k, "chains")
+            assert torch.equal(b[i][k], one[k]), (i, k, "grouped")
+
+
 def test_batch_graph_replays_are_bitwise_stable(phantom):
     chunks = _chunks(phantom)
     b = st.Batch(chunks, SIGMA, axis_center=phantom["center"], axis_direction=phantom["direction"],
